@@ -1,0 +1,7 @@
+"""FP64 CPU oracle for the batched adaptive Runge-Kutta solver.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product package.
+"""
+from .oracle import (adjoint, dense_weights, initial_step, rhs, solve,  # noqa: F401
+                     tableau)

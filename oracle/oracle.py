@@ -1,0 +1,214 @@
+"""ctypes front end of the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+A problem is a dict of numpy arrays (see paper_2210_12375_amd.workloads):
+kind[B], dim[B] (int32); y0[B, D], t0[B], t_end[B], rtol[B], atol[B],
+t_eval[B, E] (float64); optional h0[B], mu[B], A[B, D, D], eps[B, D],
+lam[B, D] and mlp = {W1, b1, W2, b2, W3, b3} with W_l stored [fan_in, fan_out].
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_METHODS = {"dopri5": 0, "tsit5": 1}
+_lib = None
+
+# Controller presets: the integral controller of the paper's benchmarks
+# (appendix A) and the PI controller (Gustafsson, exponents 0.7/5 and 0.4/5).
+I_CONTROLLER = dict(beta1=0.2, beta2=0.0)
+PI_CONTROLLER = dict(beta1=0.7 / 5, beta2=0.4 / 5)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class _Problem(C.Structure):
+    _fields_ = [("B", C.c_int32), ("D", C.c_int32), ("E", C.c_int32),
+                ("kind", _ip), ("dim", _ip), ("y0", _dp), ("t0", _dp),
+                ("t_end", _dp), ("rtol", _dp), ("atol", _dp), ("t_eval", _dp),
+                ("h0", _dp), ("mu", _dp), ("A", _dp),
+                ("n0", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32),
+                ("n3", C.c_int32),
+                ("W1", _dp), ("b1", _dp), ("W2", _dp), ("b2", _dp),
+                ("W3", _dp), ("b3", _dp), ("eps", _dp), ("lam", _dp)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("safety", C.c_double),
+                ("fac_min", C.c_double), ("fac_max", C.c_double),
+                ("max_steps", C.c_int32), ("n_threads", C.c_int32),
+                ("h_replay", _dp), ("n_replay", _ip), ("replay_cap", C.c_int32),
+                ("h_rec", _dp), ("rec_cap", C.c_int32)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if _build.needs_build():
+            _build.build()
+        lib = C.CDLL(_build.LIB)
+        lib.orc_solve.restype = C.c_int
+        lib.orc_solve.argtypes = [C.POINTER(_Problem), C.POINTER(_Options),
+                                  _dp, _dp, _ip]
+        lib.orc_adjoint.restype = C.c_int
+        lib.orc_adjoint.argtypes = [C.POINTER(_Problem), C.POINTER(_Options),
+                                    _dp, _ip, C.c_int32, _dp, _dp, _dp, _dp]
+        lib.orc_rhs.restype = None
+        lib.orc_rhs.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_double,
+                                _dp, _dp]
+        lib.orc_tableau.restype = None
+        lib.orc_tableau.argtypes = [C.c_int32, _dp, _dp, _dp, _dp]
+        lib.orc_dense_weights.restype = None
+        lib.orc_dense_weights.argtypes = [C.c_int32, C.c_double, _dp]
+        lib.orc_initial_step.restype = C.c_double
+        lib.orc_initial_step.argtypes = [C.POINTER(_Problem), C.c_int32, _ip]
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+class _Marshalled:
+    """Keeps the contiguous copies alive while the C struct points at them."""
+
+    def __init__(self, p):
+        y0 = _f64(p["y0"])
+        B, D = y0.shape
+        t_eval = p.get("t_eval")
+        t_eval = _f64(np.zeros((B, 0)) if t_eval is None else t_eval)
+        E = t_eval.shape[1]
+        keep = dict(y0=y0, t_eval=t_eval)
+        keep["kind"] = np.ascontiguousarray(p["kind"], dtype=np.int32)
+        keep["dim"] = np.ascontiguousarray(p["dim"], dtype=np.int32)
+        for k in ("t0", "t_end", "rtol", "atol"):
+            keep[k] = _f64(np.broadcast_to(p[k], (B,)))
+        for k in ("h0", "mu", "A", "eps", "lam"):
+            keep[k] = None if p.get(k) is None else _f64(p[k])
+        mlp = p.get("mlp")
+        s = _Problem()
+        s.B, s.D, s.E = B, D, E
+        if mlp is not None:
+            for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+                keep[k] = _f64(mlp[k])
+            s.n0, s.n1 = keep["W1"].shape
+            s.n2 = keep["W2"].shape[1]
+            s.n3 = keep["W3"].shape[1]
+        for k in ("y0", "t0", "t_end", "rtol", "atol", "t_eval", "h0", "mu",
+                  "A", "eps", "lam", "W1", "b1", "W2", "b2", "W3", "b3"):
+            setattr(s, k, _ptr(keep.get(k)))
+        s.kind = _ptr(keep["kind"], _ip)
+        s.dim = _ptr(keep["dim"], _ip)
+        self.s, self.keep, self.B, self.D, self.E = s, keep, B, D, E
+
+
+def _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
+             n_threads):
+    o = _Options()
+    o.method = _METHODS[method]
+    o.beta1, o.beta2, o.safety = beta1, beta2, safety
+    o.fac_min, o.fac_max = fac_min, fac_max
+    o.max_steps, o.n_threads = max_steps, n_threads
+    return o
+
+
+def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
+          beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2, fac_max=10.0,
+          max_steps=100000, n_threads=0, h_replay=None, n_replay=None,
+          record_cap=0):
+    """Solves every instance; returns a dict of numpy arrays."""
+    lib = _load()
+    m = _Marshalled(problem)
+    o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
+                 n_threads)
+    if h_replay is not None:
+        h_replay = _f64(h_replay)
+        n_replay = np.ascontiguousarray(n_replay, dtype=np.int32)
+        o.h_replay, o.n_replay = _ptr(h_replay), _ptr(n_replay, _ip)
+        o.replay_cap = h_replay.shape[1]
+    h_rec = None
+    if record_cap > 0:
+        h_rec = np.full((m.B, record_cap), np.nan)
+        o.h_rec, o.rec_cap = _ptr(h_rec), record_cap
+    y_eval = np.zeros((m.B, m.E, m.D))
+    y_final = np.zeros((m.B, m.D))
+    stats = np.zeros((5, m.B), dtype=np.int32)
+    rc = lib.orc_solve(C.byref(m.s), C.byref(o), _ptr(y_eval), _ptr(y_final),
+                       _ptr(stats, _ip))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem description")
+    out = dict(y_eval=y_eval, y_final=y_final, n_attempted=stats[0],
+               n_accepted=stats[1], n_rejected=stats[2], n_feval=stats[3],
+               status=stats[4])
+    if h_rec is not None:
+        out["h_rec"] = h_rec
+    return out
+
+
+def adjoint(problem, h_steps, n_steps, g_eval, g_final, method="dopri5",
+            n_threads=0):
+    """Discrete adjoint with the given accepted steps frozen.
+
+    Returns (dy0 [B, D], dtheta [p] or None)."""
+    lib = _load()
+    m = _Marshalled(problem)
+    o = _options(method, 0.0, 0.0, 0.9, 0.2, 10.0, 1 << 30, n_threads)
+    h_steps = _f64(h_steps)
+    n_steps = np.ascontiguousarray(n_steps, dtype=np.int32)
+    g_eval = _f64(np.zeros((m.B, m.E, m.D)) if g_eval is None else g_eval)
+    g_final = _f64(g_final)
+    dy0 = np.zeros((m.B, m.D))
+    dtheta = None
+    mlp = problem.get("mlp")
+    if mlp is not None:
+        dtheta = np.zeros(sum(np.asarray(mlp[k]).size
+                              for k in ("W1", "b1", "W2", "b2", "W3", "b3")))
+    rc = lib.orc_adjoint(C.byref(m.s), C.byref(o), _ptr(h_steps),
+                         _ptr(n_steps, _ip), h_steps.shape[1], _ptr(g_eval),
+                         _ptr(g_final), _ptr(dy0), _ptr(dtheta))
+    if rc != 0:
+        raise ValueError("oracle adjoint rejected its arguments")
+    return dy0, dtheta
+
+
+def rhs(problem, i, t, y):
+    lib = _load()
+    m = _Marshalled(problem)
+    y = _f64(y)
+    out = np.zeros_like(y)
+    lib.orc_rhs(C.byref(m.s), int(i), float(t), _ptr(y), _ptr(out))
+    return out
+
+
+def initial_step(problem, i):
+    lib = _load()
+    m = _Marshalled(problem)
+    nfe = np.zeros(1, dtype=np.int32)
+    h = lib.orc_initial_step(C.byref(m.s), int(i), _ptr(nfe, _ip))
+    return h, int(nfe[0])
+
+
+def tableau(method):
+    lib = _load()
+    c, a, b, bh = np.zeros(7), np.zeros(49), np.zeros(7), np.zeros(7)
+    lib.orc_tableau(_METHODS[method], _ptr(c), _ptr(a), _ptr(b), _ptr(bh))
+    return c, a.reshape(7, 7), b, bh
+
+
+def dense_weights(method, theta):
+    lib = _load()
+    w = np.zeros(7)
+    lib.orc_dense_weights(_METHODS[method], float(theta), _ptr(w))
+    return w
+
+
+def library_path():
+    return os.path.abspath(_build.LIB)

@@ -1,0 +1,145 @@
+"""Pins of the oracle's CNF field and discrete adjoint.
+
+CNF (appendix A, FFJORD): the one-sample Hutchinson term averaged over every
+Rademacher probe equals -trace(J) exactly, with J taken by finite differences
+of the field (not by the oracle's forward-mode tangent); a diagonal linear
+flow has a closed-form log-density change.
+
+Adjoint (section 4.2, discretize-then-optimize): the oracle's reverse sweep
+against central finite differences of the frozen-step forward map, which the
+replay mode of the forward solver computes independently.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_12375_amd import workloads as W
+
+
+def small_cnf(B=2, d=4, hidden=8, seed=7):
+    p = W.cnf_density(seed=seed, B=B, d=d, hidden=hidden)
+    return p
+
+
+def test_hutchinson_brute_force_equals_trace():
+    p = small_cnf(B=1, d=4, hidden=8)
+    d = 4
+    z = np.append(np.random.default_rng(3).standard_normal(d), 0.0)
+    t = 0.3
+    # Jacobian of g by central differences of the oracle's field
+    J = np.zeros((d, d))
+    hfd = 1e-6
+    for k in range(d):
+        e = np.zeros(d + 1)
+        e[k] = hfd
+        J[:, k] = (oracle.rhs(p, 0, t, z + e)[:d]
+                   - oracle.rhs(p, 0, t, z - e)[:d]) / (2 * hfd)
+    vals = []
+    for signs in itertools.product([-1.0, 1.0], repeat=d):
+        q = dict(p)
+        q["eps"] = np.zeros((1, d + 1))
+        q["eps"][0, :d] = signs
+        vals.append(oracle.rhs(q, 0, t, z)[d])
+        # each probe: -eps^T J eps
+        s = np.array(signs)
+        assert abs(vals[-1] + s @ J @ s) < 1e-7
+    assert abs(np.mean(vals) + np.trace(J)) < 1e-7
+
+
+def test_cnf_diag_closed_form():
+    """g(z) = lam * z: z(1) = exp(lam) x and l(1) = -sum(lam), so
+    log p(x) = log N(z(1)) + sum(lam)."""
+    B, d = 3, 5
+    rng = np.random.default_rng(11)
+    D = d + 1
+    lam = np.zeros((B, D))
+    lam[:, :d] = rng.uniform(-1, 1, (B, d))
+    eps = np.zeros((B, D))
+    eps[:, :d] = rng.choice([-1.0, 1.0], (B, d))
+    y0 = np.zeros((B, D))
+    y0[:, :d] = rng.standard_normal((B, d))
+    p = dict(kind=np.full(B, W.CNF_DIAG, np.int32), dim=np.full(B, D, np.int32),
+             y0=y0, t0=np.zeros(B), t_end=np.ones(B), rtol=np.full(B, 1e-8),
+             atol=np.full(B, 1e-10), lam=lam, eps=eps)
+    r = oracle.solve(p, method="tsit5")
+    np.testing.assert_allclose(r["y_final"][:, :d],
+                               np.exp(lam[:, :d]) * y0[:, :d], rtol=1e-6)
+    np.testing.assert_allclose(r["y_final"][:, d], -lam.sum(axis=1),
+                               rtol=1e-6)
+
+
+def frozen_loss(p, method, h, n, g_eval, g_final):
+    r = oracle.solve(p, method=method, h_replay=h, n_replay=n)
+    L = (g_final * r["y_final"]).sum()
+    if g_eval is not None and r["y_eval"].size:
+        L += (g_eval * r["y_eval"]).sum()
+    return L
+
+
+def perturb_mlp(p, w, s):
+    q = dict(p)
+    q["mlp"] = {}
+    off = 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a = p["mlp"][k]
+        q["mlp"][k] = a + s * w[off:off + a.size].reshape(a.shape)
+        off += a.size
+    return q
+
+
+def check_adjoint(p, method, with_theta, rng, n_dirs=3):
+    r = oracle.solve(p, method=method, record_cap=512)
+    assert np.all(r["status"] == 1)
+    cap = int(r["n_accepted"].max())
+    h, n = r["h_rec"][:, :cap], r["n_accepted"]
+    B, D = p["y0"].shape
+    E = p["t_eval"].shape[1] if p.get("t_eval") is not None else 0
+    g_eval = rng.standard_normal((B, E, D))
+    g_final = rng.standard_normal((B, D))
+    for i in range(B):  # padding components carry no cotangent
+        g_eval[i, :, p["dim"][i]:] = 0
+        g_final[i, p["dim"][i]:] = 0
+    dy0, dth = oracle.adjoint(p, h, n, g_eval, g_final, method=method)
+    for _ in range(n_dirs):
+        v = rng.standard_normal((B, D))
+        for i in range(B):
+            v[i, p["dim"][i]:] = 0
+        s = 1e-6
+        qp = dict(p, y0=p["y0"] + s * v)
+        qm = dict(p, y0=p["y0"] - s * v)
+        fd = (frozen_loss(qp, method, h, n, g_eval, g_final)
+              - frozen_loss(qm, method, h, n, g_eval, g_final)) / (2 * s)
+        an = (dy0 * v).sum()
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
+        if with_theta:
+            w = rng.standard_normal(dth.size)
+            fd = (frozen_loss(perturb_mlp(p, w, s), method, h, n, g_eval,
+                              g_final)
+                  - frozen_loss(perturb_mlp(p, w, -s), method, h, n, g_eval,
+                                g_final)) / (2 * s)
+            an = dth @ w
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
+
+
+@pytest.mark.parametrize("method", ["dopri5", "tsit5"])
+def test_adjoint_uneven_batch(method, rng):
+    p = W.subset(W.uneven_batch(B=64), np.arange(6))
+    p["t_end"] = np.minimum(p["t_end"], 3.0)
+    p["t_eval"] = np.sort(rng.uniform(0, 1, (6, 5)) * p["t_end"][:, None],
+                          axis=1)
+    p["t_eval"][0, 0] = 0.0  # an evaluation time at t0
+    p["t_eval"][1, -1] = p["t_end"][1]  # and one at t_end
+    check_adjoint(p, method, False, rng)
+
+
+@pytest.mark.parametrize("method", ["dopri5", "tsit5"])
+def test_adjoint_mlp(method, rng):
+    p = W.neural_ode_fit(B=3, d=3, hidden=6, n_times=4)
+    check_adjoint(p, method, True, rng)
+
+
+def test_adjoint_cnf(rng):
+    p = small_cnf(B=2, d=3, hidden=5)
+    check_adjoint(p, "dopri5", True, rng)
