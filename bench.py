@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched adaptive Runge-Kutta hot path on one MI355X.
+
+A step is one whole solve of the uneven batch: 65,536 independent instances,
+half Van der Pol (mu log-uniform on [0.1, 20]) and half linear y' = A y in 8
+dimensions, t_end ~ U[1, 50], 16 dense-output times each, rtol 1e-6,
+atol 1e-8, PI controller: solver_init (first stage, starting step, queue) and
+solver_solve (the persistent per-lane kernels) through the C ABI, inputs
+resident in HBM.  The metric is accepted instance-steps per second.
+
+The headline runs FP32 (state, norm and controller in float; time in
+double) with Dormand-Prince; FP64 and Tsit5 variants are reported beside it,
+each with its error at the stated tolerance against a tight FP64 solve.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--method", default="dopri5")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--variants", default="all",
+                    help="'all' or 'headline' (skip the side variants)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--autotune", action="store_true")
+    return ap.parse_args()
+
+
+def ensure_built():
+    from paper_2210_12375_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2210_12375_amd import build
+        build.build()
+
+
+def timed_solves(bd, dp, method, precision, steps, warmup, autotune=False):
+    """Runs warmup + steps whole solves; returns per-solve ms (init + solve),
+    per-solve ms of solver_solve alone (HIP events on the solver's stream),
+    and the statistics of the last solve."""
+    import torch
+    s = bd.Solver(dp, method=method, precision=precision)
+    if autotune:
+        bd.solver_autotune(s.cfg, s.prob, s.workspace.data_ptr(),
+                           s.workspace.numel(), s.stream.cuda_stream)
+        torch.cuda.synchronize()
+    s.close()
+    cfg, prob = s.cfg, s.prob
+    ws_ptr, ws_bytes = s.workspace.data_ptr(), s.workspace.numel()
+    stream = torch.cuda.current_stream()
+    L = bd.lib()
+    import ctypes as C
+    evs = [(torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+
+    def one(ev=None):
+        h = C.c_void_p()
+        rc = L.solver_init(C.byref(cfg), C.byref(prob), ws_ptr, ws_bytes,
+                           stream.cuda_stream, C.byref(h))
+        if rc != 0:
+            raise bd.BodeError(rc, bd.solver_last_error())
+        if ev is not None:
+            ev[0].record(stream)
+        rc = L.solver_solve(h)
+        if ev is not None:
+            ev[1].record(stream)
+        if rc != 0:
+            raise bd.BodeError(rc, bd.solver_last_error(h))
+        L.solver_destroy(h)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one(evs[k])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    solve_ms = [a.elapsed_time(b) for a, b in evs]
+    # statistics of the (deterministic) solve
+    s = bd.Solver(dp, method=method, precision=precision).solve()
+    st = {k: v.cpu().numpy() for k, v in s.stats().items()}
+    y_eval = s.y_eval.double().cpu().numpy()
+    y_final = s.y_final.double().cpu().numpy()
+    s.close()
+    return wall, solve_ms, st, y_eval, y_final
+
+
+def error_at_tolerance(p, y_eval, y_final, ref, idx):
+    """Global error over a sample against a tight FP64 solve, in units of
+    the requested tolerance: max |y - ref| / (rtol |ref| + atol) over every
+    output component (median and maximum over instances)."""
+    a = np.concatenate([y_eval[idx].reshape(len(idx), -1),
+                        y_final[idx].reshape(len(idx), -1)], axis=1)
+    b = np.concatenate([ref[0].reshape(len(idx), -1),
+                        ref[1].reshape(len(idx), -1)], axis=1)
+    tol = p["rtol"][idx][:, None] * np.abs(b) + p["atol"][idx][:, None]
+    e = (np.abs(a - b) / tol).max(axis=1)
+    return float(np.median(e)), float(e.max())
+
+
+def cpu_baseline(p, method, seconds):
+    """The FP64 oracle on the host cores over whole copies of a bounded
+    sample of the same batch."""
+    import oracle
+    nt = os.cpu_count() or 1
+    try:
+        nt = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    from paper_2210_12375_amd import workloads as W
+    n = 8192
+    q = W.subset(p, np.arange(n))
+    t0 = time.perf_counter()
+    r = oracle.solve(q, method=method, n_threads=nt)
+    dt = time.perf_counter() - t0
+    reps = max(1, int(seconds / max(dt, 1e-3)))
+    acc = int(r["n_accepted"].sum())
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.solve(q, method=method, n_threads=nt)
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": acc / dt, "unit": "accepted instance-steps/s",
+            "cores": nt, "kind": "oracle",
+            "sample": f"first {n} of the 65,536 instances (FP64 oracle, "
+                      f"{method}, PI), {reps} repetitions, "
+                      f"{dt * 1e3:.1f} ms per pass"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                                   "--gpus must be 1"}), flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(3)
+    ensure_built()
+    from paper_2210_12375_amd import binding as bd
+    from paper_2210_12375_amd import roofline as rl
+    from paper_2210_12375_amd import workloads as W
+
+    p = W.uneven_batch()
+    B = p["y0"].shape[0]
+    variants = [(a.method, a.precision)]
+    if a.variants == "all":
+        for m in ("dopri5", "tsit5"):
+            for pr in ("fp32", "fp64"):
+                if (m, pr) not in variants:
+                    variants.append((m, pr))
+    # tight FP64 reference on a sample (GPU, parity-tested against the oracle)
+    idx = np.random.default_rng(7).choice(B, 1024, replace=False)
+    q = W.subset(p, idx)
+    q["rtol"][:] = 1e-12
+    q["atol"][:] = 1e-14
+    sref = bd.Solver(bd.device_problem(q, "fp64"), method="dopri5",
+                     precision="fp64").solve()
+    ref = (sref.y_eval.cpu().numpy(), sref.y_final.cpu().numpy())
+    sref.close()
+
+    results = {}
+    for (m, pr) in variants:
+        dp = bd.device_problem(p, pr)
+        wall, solve_ms, st, ye, yf = timed_solves(
+            bd, dp, m, pr, a.steps if (m, pr) == variants[0] else
+            max(3, a.steps // 2), a.warmup, autotune=a.autotune)
+        acc = int(st["n_accepted"].sum())
+        att = int(st["n_attempted"].sum())
+        emitted = np.full(B, p["t_eval"].shape[1])
+        flops = rl.analytic_flops(m, p["kind"], p["dim"], st["n_attempted"],
+                                  emitted)
+        solve_avg = float(np.mean(solve_ms))
+        results[(m, pr)] = dict(
+            ms_per_step=wall, solve_ms=solve_avg, accepted=acc,
+            attempted=att, value=acc / (wall * 1e-3),
+            flops=flops, ok=bool(np.all(st["status"] == 1)),
+            steps_p50=int(np.median(st["n_accepted"])),
+            steps_max=int(st["n_accepted"].max()),
+            steps_hist=np.histogram(st["n_accepted"],
+                                    bins=[0, 50, 100, 200, 400, 800, 1600,
+                                          3200, 1 << 30])[0].tolist(),
+            err_at_tol=error_at_tolerance(p, ye, yf, ref, idx))
+        print(f"# {m} {pr}: {wall:.3f} ms/solve, solve kernel "
+              f"{solve_avg:.3f} ms, {acc} accepted steps", file=sys.stderr,
+              flush=True)
+
+    head = results[variants[0]]
+    peak = (rl.PEAK["fp64_vector_tflops"] if a.precision == "fp64"
+            else rl.PEAK["fp32_vector_tflops"])
+    achieved = head["flops"] / (head["solve_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "accepted instance-steps/sec",
+        "value": head["value"],
+        "unit": "instance-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.precision != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "uneven batch: 65,536 instances, half Van der "
+                               "Pol (mu log-U[0.1,20], D=2), half linear "
+                               "y'=Ay (D=8), t_end~U[1,50], 16 dense-output "
+                               "times, rtol 1e-6 atol 1e-8, PI controller",
+                   "method": variants[0][0], "precision": variants[0][1],
+                   "instances": B, "parallelism": "1 GPU, instances over "
+                                                  "lanes"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None,
+                     "kernel": "persistent solve (Van der Pol + linear "
+                               "kernels, concurrent)",
+                     "critical_path_steps": head["steps_max"]},
+        "accuracy": {f"{m}/{pr}": {"err_in_tol_units_median":
+                                   r["err_at_tol"][0],
+                                   "err_in_tol_units_max": r["err_at_tol"][1],
+                                   "sample": 1024, "reference":
+                                   "GPU FP64 dopri5 at rtol 1e-12"}
+                     for (m, pr), r in results.items()},
+        "variants": {f"{m}/{pr}": {k: r[k] for k in
+                                   ("value", "ms_per_step", "solve_ms",
+                                    "accepted", "attempted", "steps_p50",
+                                    "steps_max", "steps_hist", "ok")}
+                     for (m, pr), r in results.items()},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, a.method, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

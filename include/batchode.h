@@ -1,0 +1,210 @@
+/*
+ * batchode: a batched adaptive explicit Runge-Kutta solver for MI355X (gfx950).
+ *
+ * It implements the parallel solving method of Lienen & Guennemann,
+ * "torchode: A Parallel ODE Solver for PyTorch" (arXiv 2210.12375): a batch of
+ * independent initial value problems is advanced together, and every instance
+ * keeps its own time, step size, error estimate, step-size-controller state
+ * and accept/reject decision (section 3, "Design & Features"; section 4.1
+ * shows why a shared step size is wrong for uneven batches).  Evaluation
+ * times are per instance and answered by dense output (section 3, "What slows
+ * torchode down?").
+ *
+ * Calling convention
+ *  - Plain C ABI: no C++ exception crosses it.  Every call returns BODE_OK (0)
+ *    or a negative BODE_E* code; solver_last_error() gives the text.
+ *  - Device pointers are HIP device allocations owned by the caller.  Inputs
+ *    are borrowed: they must stay valid and unchanged until solver_destroy()
+ *    (the backward pass re-reads y0 and the parameters).  The library never
+ *    allocates device memory: all scratch lives in the caller's workspace of
+ *    solver_workspace_size() bytes.
+ *  - All device work is enqueued on the caller's stream (a hipStream_t passed
+ *    as void*) and is asynchronous unless a call says otherwise.
+ *  - Per-instance numerical outcomes are a status (BODE_SUCCESS,
+ *    BODE_MAX_STEPS, ...), never an error code.
+ *
+ * Layout: every per-instance array is instance-major ("[B, D]" means
+ * B rows of D elements, row stride D).  State-typed arrays are double in
+ * BODE_FP64 mode and float otherwise; times are always double.
+ */
+#ifndef BATCHODE_H
+#define BATCHODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- enumerations ------------------------------------------------------ */
+
+/* Runge-Kutta pairs (paper appendix A: "dopri5" in every experiment; "tsit5"
+ * is also provided).  Both are 7-stage, FSAL, order 5 with an embedded
+ * order-4 error estimate and a fourth-order continuous extension.          */
+#define BODE_DOPRI5 0
+#define BODE_TSIT5 1
+
+/* Arithmetic of the solve.
+ *  FP64: state, stages, norm, controller and time in double.
+ *  FP32: state, stages, norm and controller in float; time in double.
+ *  BF16: as FP32, but neural right-hand sides run their GEMMs on BF16 MFMA
+ *        with FP32 accumulation (analytic right-hand sides behave as FP32). */
+#define BODE_FP64 0
+#define BODE_FP32 1
+#define BODE_BF16 2
+
+/* Right-hand-side families.  ANALYTIC batches mix, per instance (kind[]),
+ *  BODE_KIND_VDP:    x' = v, v' = mu (1 - x^2) v - x  (section 4.1, Eq. eq:vdp)
+ *  BODE_KIND_LINEAR: y' = A y with A of size dim x dim, dim <= 8.          */
+#define BODE_RHS_ANALYTIC 0
+#define BODE_RHS_MLP 2
+#define BODE_RHS_CNF 3
+
+#define BODE_KIND_VDP 0
+#define BODE_KIND_LINEAR 1
+
+/* Per-instance status. */
+#define BODE_RUNNING 0
+#define BODE_SUCCESS 1
+#define BODE_MAX_STEPS 2
+#define BODE_DT_UNDERFLOW 3
+#define BODE_INVALID 4
+
+/* Error codes. */
+#define BODE_OK 0
+#define BODE_EINVAL (-1)       /* bad argument or configuration              */
+#define BODE_EUNSUPPORTED (-2) /* valid but not built (e.g. CNF in FP64 MFMA) */
+#define BODE_EHIP (-3)         /* a HIP runtime call failed                   */
+#define BODE_ESTATE (-4)       /* call out of order (e.g. eval before a step) */
+
+/* ---- configuration ----------------------------------------------------- */
+
+typedef struct {
+  int32_t method;    /* BODE_DOPRI5 | BODE_TSIT5                              */
+  int32_t precision; /* BODE_FP64 | BODE_FP32 | BODE_BF16                     */
+  int32_t rhs;       /* BODE_RHS_*                                            */
+  int32_t B;         /* instances, >= 1                                       */
+  int32_t D;         /* row stride of state arrays: ANALYTIC <= 8; MLP = d;
+                        CNF = d + 1 (the last component is the log-density)   */
+  int32_t E;         /* evaluation times per instance, >= 0                   */
+  int32_t max_steps; /* attempted steps per instance before BODE_MAX_STEPS    */
+  /* Step-size controller (section 3: the PID family generalises the
+   * integral controller; appendix C).  After an accepted step with error
+   * norm err the step is scaled by
+   *   clamp(safety * err^-beta1 * err_prev^beta2, fac_min, fac_max),
+   * capped at 1 right after a rejection; after a rejected step by
+   *   max(fac_min, safety * err^-1/5).  beta2 = 0 is the integral controller;
+   * beta1 = 0.14, beta2 = 0.08 is Gustafsson's PI controller.              */
+  double beta1, beta2, safety, fac_min, fac_max;
+  int32_t record_cap; /* attempted step sizes kept per instance (0: none);
+                         solver_backward needs >= the largest attempt count */
+  int32_t keep_dense; /* 1: keep the last accepted step's interpolant so
+                         solver_eval can answer queries                      */
+  int32_t mlp_hidden; /* MLP / CNF hidden width (both hidden layers)         */
+  int32_t tune_block; /* launch tuning (0 = library / autotuned default)     */
+  int32_t tune_lanes;
+} bode_config;
+
+/* Problem description: device pointers (NULL where not used). */
+typedef struct {
+  const void* y0;       /* [B, D] initial states (padding columns ignored)   */
+  const double* t0;     /* [B]                                               */
+  const double* t_end;  /* [B], t_end >= t0                                  */
+  const double* rtol;   /* [B], >= 0                                         */
+  const double* atol;   /* [B], >= 0, not both zero                          */
+  const double* t_eval; /* [B, E], each row non-decreasing within [t0, t_end]*/
+  const double* h0;     /* [B] first step, or NULL for Hairer's rule          */
+  const int32_t* kind;  /* [B] BODE_KIND_* (ANALYTIC only)                    */
+  const int32_t* dim;   /* [B] true dimension: VDP 2, LINEAR 1..8 (ANALYTIC)  */
+  const void* mu;       /* [B] Van der Pol damping (ANALYTIC)                */
+  const void* A;        /* [B, D, D] row-major linear systems (ANALYTIC)     */
+  /* MLP / CNF parameters, state-typed, W_l stored [fan_in, fan_out]:
+   * x = [y, t] (MLP) or [z, t] (CNF); a1 = tanh(x W1 + b1);
+   * a2 = tanh(a1 W2 + b2); out = a2 W3 + b3.                              */
+  const void *W1, *b1, *W2, *b2, *W3, *b3;
+  const void* eps;      /* [B, D] Rademacher probes (CNF; first D-1 used)    */
+  void* y_eval;         /* [B, E, D] output: solution at t_eval              */
+  void* y_final;        /* [B, D]    output: state at t_end (or at failure)  */
+} bode_problem;
+
+typedef struct bode_solver bode_solver;
+
+/* ---- calls ------------------------------------------------------------- */
+
+/* Bytes of device workspace solver_init needs for cfg (0 if cfg invalid). */
+size_t solver_workspace_size(const bode_config* cfg);
+
+/* Validates cfg and the host-visible parts of p, lays out the workspace and
+ * enqueues the initialisation of every instance on `stream`: the first stage
+ * k1 = f(t0, y0), Hairer's starting step (Solving ODEs I, II.4) unless h0 is
+ * given, answers for evaluation times equal to t0, and per-instance checks
+ * of the device inputs (a bad instance gets status BODE_INVALID).
+ * On success *out is a new handle.                                          */
+int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
+                size_t workspace_bytes, void* stream, bode_solver** out);
+
+/* Every RUNNING instance attempts up to n_attempts further steps (each
+ * accepted or rejected by its own error norm).  If n_running_host is not
+ * NULL the call synchronises the stream and stores the number of instances
+ * still RUNNING there.                                                      */
+int solver_step(bode_solver* s, int32_t n_attempts, int32_t* n_running_host);
+
+/* Steps every instance to completion (t_end, max_steps or a failure).
+ * Asynchronous.                                                             */
+int solver_solve(bode_solver* s);
+
+/* Dense output of each instance's last accepted step at its own query time:
+ * for t_query[i] in [t_prev_i, t_i] writes y_out[i, :] and qstatus[i] = 0,
+ * otherwise qstatus[i] = 1 and y_out[i, :] = NaN.  Needs cfg.keep_dense.
+ * t_query [B] double, y_out [B, D] state-typed, qstatus [B] int32: device.  */
+int solver_eval(bode_solver* s, const double* t_query, void* y_out,
+                int32_t* qstatus);
+
+/* Discrete adjoint through the accepted steps (step sizes and accept
+ * decisions frozen; paper section 4.2 trains by backpropagating through the
+ * solver).  g_y_eval [B, E, D] (may be NULL) and g_y_final [B, D] are the
+ * cotangents of y_eval and y_final; writes dy0 [B, D] and, for MLP / CNF,
+ * dtheta = gradients of (W1, b1, W2, b2, W3, b3) concatenated, summed over
+ * instances.  Needs a completed solve with cfg.record_cap covering every
+ * instance's accepted steps.                                               */
+int solver_backward(bode_solver* s, const void* g_y_eval, const void* g_y_final,
+                    void* dy0, void* dtheta);
+
+/* Per-instance statistics (section 3: total and accepted steps are collected
+ * by default), copied asynchronously into device int32 arrays [B] (any may
+ * be NULL): attempted, accepted and rejected steps, right-hand-side
+ * evaluations (1 + starting-step probe + 6 per attempt) and status.        */
+int solver_get_stats(const bode_solver* s, int32_t* n_attempted,
+                     int32_t* n_accepted, int32_t* n_rejected,
+                     int32_t* n_feval, int32_t* status);
+
+/* The step record, copied into device arrays h [B, record_cap] (double):
+ * the size of every attempted step in order, negated for rejected attempts,
+ * and n [B] (int32): the number of attempts (it may exceed record_cap, in
+ * which case only the first record_cap are kept).                          */
+int solver_get_steps(const bode_solver* s, double* h, int32_t* n);
+
+/* Times launch candidates for this configuration on the caller's problem
+ * (outputs are overwritten) and keeps the fastest for later solver_init
+ * calls with the same shape.  Synchronous.                                  */
+int solver_autotune(const bode_config* cfg, const bode_problem* p,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Releases the host handle (no device memory is owned). */
+void solver_destroy(bode_solver* s);
+
+/* Text of the last error of s, or of the calling thread if s is NULL. */
+const char* solver_last_error(const bode_solver* s);
+
+/* Host-side copy of the constants the kernels use, for checks without a GPU:
+ * c[7], a[49] row-major, b[7], e[7] (= b - bhat), dense[28] with
+ * w_j(theta) = sum_m dense[j*4 + m] theta^(m+1).  Returns BODE_EINVAL for an
+ * unknown method.                                                          */
+int solver_tableau(int32_t method, double* c, double* a, double* b, double* e,
+                   double* dense);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -10,25 +10,39 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["tableau.c", "rhs.c", "solve.c", "adjoint.c"]
 LIB = os.path.join(HERE, "liboracle.so")
+# The same source with every a*b+c contracted into a fused multiply-add.  It
+# is not a second oracle: the tests use it only to find instances whose step
+# counts change under a 1-ulp change of rounding (see tests/gpu_helpers.py).
+LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
-           "-Wall", "-Wextra", "-shared", "-o", LIB + ".tmp"]
+def _build_one(out, contract, verbose):
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", f"-ffp-contract={contract}",
+           "-fPIC", "-Wall", "-Wextra", "-shared", "-o", out + ".tmp"]
+    if contract == "fast":
+        cmd.insert(3, "-mfma")
     cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False) -> str:
+    _build_one(LIB, "off", verbose)
+    _build_one(LIB_FMA, "fast", verbose)
     return LIB
 
 
 def needs_build() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    deps = SOURCES + ["oracle.h"]
-    return any(os.path.getmtime(os.path.join(HERE, s)) > t for s in deps)
+    for lib in (LIB, LIB_FMA):
+        if not os.path.exists(lib):
+            return True
+        t = os.path.getmtime(lib)
+        deps = SOURCES + ["oracle.h"]
+        if any(os.path.getmtime(os.path.join(HERE, s)) > t for s in deps):
+            return True
+    return False
 
 
 if __name__ == "__main__":

@@ -80,16 +80,27 @@ typedef struct {
   double beta1, beta2, safety, fac_min, fac_max;
   int32_t max_steps;     /* attempted steps per instance                     */
   int32_t n_threads;     /* OpenMP threads (<= 0: library default)           */
-  /* Replay: if h_replay != NULL, instance i takes exactly n_replay[i] steps
-   * with sizes h_replay[i, :], all accepted, no controller (fixed-step mode
-   * and the replay of a recorded step sequence).                           */
+  /* Replay: if h_replay != NULL, instance i makes exactly n_replay[i]
+   * attempts with sizes |h_replay[i, :]|, no controller deciding: a positive
+   * entry is an accepted step, a negative entry a rejected attempt (computed,
+   * then discarded).  The last positive entry is the step that ends on t_end.
+   * This is the fixed-step mode and the replay of a recorded sequence.     */
   const double* h_replay;
   const int32_t* n_replay;
   int32_t replay_cap;
-  /* Recording: if h_rec != NULL, the size of every accepted step is written
-   * to h_rec[i, n] for n < rec_cap.                                         */
+  /* Optional [B]: 0 marks a record that stopped before t_end (its last
+   * accepted step is an ordinary step); NULL means every record ends there. */
+  const int32_t* replay_final;
+  /* Recording: if h_rec != NULL, the size of every attempted step is written
+   * to h_rec[i, n] for n < rec_cap, negated when the attempt was rejected.  */
   double* h_rec;
   int32_t rec_cap;
+  /* Replay diagnostics: if err_rec != NULL, the error norm of every replayed
+   * attempt is written to err_rec[i, n] (n < replay_cap), computed exactly as
+   * an adaptive step computes it, and if hprop_rec != NULL the step size the
+   * controller would propose next, given the replayed decisions so far.    */
+  double* err_rec;
+  double* hprop_rec;
 } orc_options;
 
 /* Solves every instance.  Outputs:

@@ -14,6 +14,7 @@ from . import build as _build
 
 _METHODS = {"dopri5": 0, "tsit5": 1}
 _lib = None
+_lib_fma = None
 
 # Controller presets: the integral controller of the paper's benchmarks
 # (appendix A) and the PI controller (Gustafsson, exponents 0.7/5 and 0.4/5).
@@ -41,11 +42,21 @@ class _Options(C.Structure):
                 ("fac_min", C.c_double), ("fac_max", C.c_double),
                 ("max_steps", C.c_int32), ("n_threads", C.c_int32),
                 ("h_replay", _dp), ("n_replay", _ip), ("replay_cap", C.c_int32),
-                ("h_rec", _dp), ("rec_cap", C.c_int32)]
+                ("replay_final", _ip),
+                ("h_rec", _dp), ("rec_cap", C.c_int32), ("err_rec", _dp),
+                ("hprop_rec", _dp)]
 
 
-def _load():
-    global _lib
+def _load(variant=None):
+    global _lib, _lib_fma
+    if variant == "fma":
+        if _lib_fma is None:
+            _load()
+            lib = C.CDLL(_build.LIB_FMA)
+            lib.orc_solve.restype = C.c_int
+            lib.orc_solve.argtypes = _lib.orc_solve.argtypes
+            _lib_fma = lib
+        return _lib_fma
     if _lib is None:
         if _build.needs_build():
             _build.build()
@@ -123,9 +134,13 @@ def _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
 def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
           beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2, fac_max=10.0,
           max_steps=100000, n_threads=0, h_replay=None, n_replay=None,
-          record_cap=0):
-    """Solves every instance; returns a dict of numpy arrays."""
-    lib = _load()
+          record_cap=0, replay_errors=False, variant=None,
+          replay_final=None):
+    """Solves every instance; returns a dict of numpy arrays.
+
+    variant="fma" runs the same source compiled with contracted multiply-adds
+    (a rounding probe for the tests, not a reference)."""
+    lib = _load(variant)
     m = _Marshalled(problem)
     o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
                  n_threads)
@@ -134,6 +149,14 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
         n_replay = np.ascontiguousarray(n_replay, dtype=np.int32)
         o.h_replay, o.n_replay = _ptr(h_replay), _ptr(n_replay, _ip)
         o.replay_cap = h_replay.shape[1]
+        if replay_final is not None:
+            replay_final = np.ascontiguousarray(replay_final, dtype=np.int32)
+            o.replay_final = _ptr(replay_final, _ip)
+    err_rec = hprop = None
+    if replay_errors:
+        err_rec = np.full((m.B, o.replay_cap), np.nan)
+        hprop = np.full((m.B, o.replay_cap), np.nan)
+        o.err_rec, o.hprop_rec = _ptr(err_rec), _ptr(hprop)
     h_rec = None
     if record_cap > 0:
         h_rec = np.full((m.B, record_cap), np.nan)
@@ -150,7 +173,26 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
                status=stats[4])
     if h_rec is not None:
         out["h_rec"] = h_rec
+    if err_rec is not None:
+        out["err_rec"] = err_rec
+        out["hprop_rec"] = hprop
     return out
+
+
+def accepted_steps(h_rec, n_attempted):
+    """Accepted step sizes (left-aligned) and their counts from a signed
+    attempt record."""
+    h_rec = np.asarray(h_rec)
+    B = h_rec.shape[0]
+    n_acc = np.zeros(B, np.int32)
+    out = np.zeros_like(h_rec)
+    for i in range(B):
+        row = h_rec[i, :n_attempted[i]]
+        a = row[row > 0]
+        out[i, :a.size] = a
+        n_acc[i] = a.size
+    cap = max(1, int(n_acc.max())) if B else 1
+    return out[:, :cap], n_acc
 
 
 def adjoint(problem, h_steps, n_steps, g_eval, g_final, method="dopri5",

@@ -150,6 +150,10 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
     const int replay = O->h_replay != NULL;
     const double* hr = replay ? O->h_replay + (long)i * O->replay_cap : NULL;
     const int nr = replay ? O->n_replay[i] : 0;
+    int last_acc = -1; /* index of the replay's final accepted step */
+    for (int q = 0; q < nr && q < (replay ? O->replay_cap : 0); ++q)
+      if (hr[q] > 0.0) last_acc = q;
+    const int ends = !replay || !O->replay_final || O->replay_final[i];
     double t = P->t0[i];
     for (int q = 0; q < n; ++q) y[q] = P->y0[(long)i * D + q];
     orc_rhs(P, i, t, y, k[0]);
@@ -163,7 +167,9 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
     if (te == t)
       status = ORC_SUCCESS;
     else if (replay)
-      status = (nr > 0 && nr <= O->replay_cap) ? ORC_RUNNING : ORC_INVALID;
+      status = (nr > 0 && nr <= O->replay_cap && (last_acc >= 0 || !ends))
+                   ? ORC_RUNNING
+                   : ORC_INVALID;
     else
       h = P->h0 ? P->h0[i] : hairer_start(P, i, k[0], &nfe);
 
@@ -176,9 +182,15 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
       }
       int last;
       double hs;
+      int replay_reject = 0;
       if (replay) {
-        hs = hr[natt];
-        last = (natt == nr - 1);
+        if (natt >= nr) { /* sequence exhausted before the end */
+          status = ORC_MAX_STEPS;
+          break;
+        }
+        hs = fabs(hr[natt]);
+        replay_reject = hr[natt] < 0.0;
+        last = ends && (natt == last_acc);
       } else {
         last = (t + h >= te);
         hs = last ? te - t : h;
@@ -196,19 +208,18 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
       nfe += 6;
       natt += 1;
 
-      int accept = 1;
-      double err = 0.0, fac = 1.0;
-      if (!replay) {
-        double acc = 0.0;
-        for (int q = 0; q < n; ++q) {
-          double eq = 0.0;
-          for (int j = 0; j < 7; ++j) eq += e[j] * k[j][q];
-          eq *= hs;
-          const double sc = atol + rtol * fmax(fabs(y[q]), fabs(ynew[q]));
-          acc += (eq / sc) * (eq / sc);
-        }
-        err = sqrt(acc / n);
-        accept = err < 1.0;
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) {
+        double eq = 0.0;
+        for (int j = 0; j < 7; ++j) eq += e[j] * k[j][q];
+        eq *= hs;
+        const double sc = atol + rtol * fmax(fabs(y[q]), fabs(ynew[q]));
+        acc += (eq / sc) * (eq / sc);
+      }
+      const double err = sqrt(acc / n);
+      int accept = replay ? !replay_reject : err < 1.0;
+      double fac = 1.0;
+      {
         if (!isfinite(err))
           fac = O->fac_min;
         else if (accept) {
@@ -223,6 +234,12 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
           fac = fmax(O->fac_min, O->safety * pow(err, -1.0 / 5.0));
         }
       }
+      if (O->h_rec && natt <= O->rec_cap)
+        O->h_rec[(long)i * O->rec_cap + natt - 1] = accept ? hs : -hs;
+      if (replay && O->err_rec)
+        O->err_rec[(long)i * O->replay_cap + natt - 1] = err;
+      if (replay && O->hprop_rec)
+        O->hprop_rec[(long)i * O->replay_cap + natt - 1] = hs * fac;
       if (accept) {
         const double tnew = last ? te : t + hs;
         while (cursor < E && teval[cursor] <= tnew) {
@@ -230,8 +247,6 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
           emit(O->method, theta, hs, y, k, n, yev + (long)cursor * D);
           ++cursor;
         }
-        if (O->h_rec && nacc < O->rec_cap)
-          O->h_rec[(long)i * O->rec_cap + nacc] = hs;
         t = tnew;
         memcpy(y, ynew, sizeof(double) * n);
         memcpy(k[0], k[6], sizeof(double) * n); /* FSAL */

@@ -1,0 +1,563 @@
+// Persistent per-lane solver for analytic right-hand sides.
+//
+// Paper section 3: every instance of the batch keeps its own time, step size,
+// error estimate, controller state and accept/reject decision; section 4.1
+// (Eq. eq:vdp) shows why: Van der Pol oscillators of different stiffness
+// need very different step sequences.  Here one lane owns one instance at a
+// time and keeps its whole state (y, the seven stages, t, h, controller state,
+// counters, evaluation cursor) in registers for as long as the instance runs.
+// There is no per-step launch, no host round trip and no "overhanging"
+// evaluation of finished instances (appendix B): a lane whose instance ends
+// takes the next one from a device-side queue (work stealing over instances),
+// so uneven step counts do not idle the batch.
+//
+// The dynamics are cheap (section 4.2 / appendix A: for Van der Pol the loop,
+// not the model, is the cost), so the kernel is bound by vector-ALU latency:
+// the critical path is the longest instance's steps times the latency of one
+// step.  Van der Pol and linear instances run in separate kernels so each gets
+// the register allocation its own state needs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "analytic.hpp"
+#include "common.hpp"
+#include "tableau.hpp"
+
+namespace bode {
+
+// ---- right-hand sides ------------------------------------------------------
+
+template <typename R>
+struct VdpField {
+  static constexpr int N = 2;
+  R mu;
+  __device__ void load(const AnalyticArgs<R>& a, int i, int) { mu = a.mu[i]; }
+  // x' = v, v' = mu (1 - x^2) v - x
+  __device__ void operator()(const R* y, R* out) const {
+    const R x = y[0], v = y[1];
+    out[0] = v;
+    out[1] = mu * (R(1) - x * x) * v - x;
+  }
+};
+
+template <typename R>
+struct LinearField {
+  static constexpr int N = 8;
+  R A[8][8];
+  __device__ void load(const AnalyticArgs<R>& a, int i, int dim) {
+    const R* Ai = a.A + (long)i * a.D * a.D;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        A[r][c] = (r < dim && c < dim) ? Ai[(long)r * a.D + c] : R(0);
+  }
+  __device__ void operator()(const R* y, R* out) const {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc += A[r][c] * y[c];
+      out[r] = acc;
+    }
+  }
+};
+
+// Stage j takes part in the interpolant (Dormand-Prince's stage 2 does not).
+template <class M>
+__host__ __device__ constexpr bool dense_uses(int j) {
+  return M::P[j][0] != 0.0 || M::P[j][1] != 0.0 || M::P[j][2] != 0.0 ||
+         M::P[j][3] != 0.0;
+}
+
+// ---- one lane's instance -----------------------------------------------------
+
+template <typename R, int N>
+struct Lane {
+  R y[N];
+  R k[7][N];
+  double t, te, next_te;
+  R h, err_prev, rtol, atol;
+  int32_t n_att, n_acc, n_rej, n_fe, status, cursor, prev_rej, dim, inst;
+};
+
+template <typename R, int N>
+__device__ void write_row(R* row, int D, const R* v, int dim) {
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (q < D) row[q] = q < dim ? v[q] : R(0);
+  for (int q = N; q < D; ++q) row[q] = R(0);
+}
+
+template <typename R, int N>
+__device__ void fill_nan_row(R* row, int D, int dim) {
+  for (int q = 0; q < D; ++q) row[q] = q < dim ? quiet_nan<R>() : R(0);
+}
+
+template <typename R, int N>
+__device__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<R, N>& L) {
+  const State<R>& s = a.st;
+  L.inst = i;
+  L.dim = a.dim[i];
+  L.t = s.t[i];
+  L.te = a.t_end[i];
+  L.h = s.h[i];
+  L.err_prev = s.err_prev[i];
+  L.rtol = R(a.rtol[i]);
+  L.atol = R(a.atol[i]);
+  L.n_att = s.n_att[i];
+  L.n_acc = s.n_acc[i];
+  L.n_rej = s.n_rej[i];
+  L.n_fe = s.n_fe[i];
+  L.status = s.status[i];
+  L.cursor = s.cursor[i];
+  L.prev_rej = s.prev_rej[i];
+  L.next_te = L.cursor < a.E ? a.t_eval[(long)i * a.E + L.cursor] : INFINITY;
+  const R* yr = s.y + (long)i * a.D;
+  const R* kr = s.k1 + (long)i * a.D;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    L.y[q] = q < L.dim ? yr[q] : R(0);
+    L.k[0][q] = q < L.dim ? kr[q] : R(0);
+  }
+}
+
+template <typename R, int N>
+__device__ void store_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
+  const State<R>& s = a.st;
+  const int i = L.inst;
+  s.t[i] = L.t;
+  s.h[i] = L.h;
+  s.err_prev[i] = L.err_prev;
+  s.n_att[i] = L.n_att;
+  s.n_acc[i] = L.n_acc;
+  s.n_rej[i] = L.n_rej;
+  s.n_fe[i] = L.n_fe;
+  s.status[i] = L.status;
+  s.cursor[i] = L.cursor;
+  s.prev_rej[i] = L.prev_rej;
+  write_row<R, N>(s.y + (long)i * a.D, a.D, L.y, L.dim);
+  write_row<R, N>(s.k1 + (long)i * a.D, a.D, L.k[0], L.dim);
+}
+
+// Writes the final state, and NaN for evaluation times never reached.
+template <typename R, int N>
+__device__ void finish_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
+  store_lane(a, L);
+  write_row<R, N>(a.y_final + (long)L.inst * a.D, a.D, L.y, L.dim);
+  if (L.status != kSuccess)
+    for (int e = L.cursor; e < a.E; ++e)
+      fill_nan_row<R, N>(a.y_eval + ((long)L.inst * a.E + e) * a.D, a.D,
+                         L.dim);
+}
+
+// One attempted step of one instance (accept or reject), in the order of the
+// reference algorithm: stages, error norm, controller, dense output, commit.
+template <typename R, class M, class F>
+__device__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
+                        const F& f) {
+  constexpr int N = F::N;
+  if (L.n_att >= a.ctrl.max_steps) {
+    L.status = kMaxSteps;
+    return;
+  }
+  const bool last = L.t + double(L.h) >= L.te;
+  const R hs = last ? R(L.te - L.t) : L.h;
+
+  // Stages 2..7: Y_s = y + h sum_{j<s} a_sj k_j, k_s = f(t + c_s h, Y_s).
+  // (The fields here are autonomous, so the stage time is not formed.)
+  R Y[N];
+#pragma unroll
+  for (int s = 1; s < 7; ++s) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R acc = R(0);
+#pragma unroll
+      for (int j = 0; j < s; ++j)
+        if (M::A[s][j] != 0.0) acc += R(M::A[s][j]) * L.k[j][q];
+      Y[q] = L.y[q] + hs * acc;
+    }
+    f(Y, L.k[s]);
+  }
+  L.n_fe += 6;
+  L.n_att += 1;
+
+  // Weighted RMS norm of the embedded error estimate over the true dimension.
+  R acc = R(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    if (q < L.dim) {
+      R eq = R(0);
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+        if (M::E[j] != 0.0) eq += R(M::E[j]) * L.k[j][q];
+      eq *= hs;
+      const R sc = L.atol + L.rtol * rmax(rabs(L.y[q]), rabs(Y[q]));
+      const R r = eq / sc;
+      acc += r * r;
+    }
+  }
+  const R err = rsqrt_(acc / R(L.dim));
+  const bool accept = err < R(1);
+  // Attempt record: every attempted step size, negated when rejected.
+  if (a.h_rec != nullptr && L.n_att <= a.rec_cap)
+    a.h_rec[(long)L.inst * a.rec_cap + L.n_att - 1] =
+        accept ? double(hs) : -double(hs);
+
+  R fac;
+  const Ctrl& c = a.ctrl;
+  if (!__builtin_isfinite(err)) {
+    fac = R(c.fac_min);
+  } else if (accept) {
+    if (err == R(0)) {
+      fac = R(c.fac_max);
+    } else {
+      fac = R(c.safety) * rpow(err, R(-c.beta1));
+      if (c.beta2 != 0.0) fac *= rpow(L.err_prev, R(c.beta2));
+      fac = rmin(R(c.fac_max), rmax(R(c.fac_min), fac));
+    }
+    if (L.prev_rej) fac = rmin(R(1), fac);
+  } else {
+    fac = rmax(R(c.fac_min), R(c.safety) * rpow(err, R(-0.2)));
+  }
+
+  if (accept) {
+    const double tnew = last ? L.te : L.t + double(hs);
+    // Dense output at this instance's own evaluation times in (t, t_new]
+    // (Horner in theta, then the stage combination).
+    while (L.next_te <= tnew) {
+      const R th = R((L.next_te - L.t) / double(hs));
+      R w[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+        w[j] = th * (R(M::P[j][0]) +
+                     th * (R(M::P[j][1]) +
+                           th * (R(M::P[j][2]) + th * R(M::P[j][3]))));
+      R out[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s2 = R(0);
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+          if (dense_uses<M>(j)) s2 += w[j] * L.k[j][q];
+        out[q] = L.y[q] + hs * s2;
+      }
+      write_row<R, N>(a.y_eval + ((long)L.inst * a.E + L.cursor) * a.D, a.D,
+                      out, L.dim);
+      L.cursor += 1;
+      L.next_te = L.cursor < a.E
+                      ? a.t_eval[(long)L.inst * a.E + L.cursor]
+                      : INFINITY;
+    }
+    if (a.keep_dense) {
+      const int i = L.inst;
+      a.dk.t_prev[i] = L.t;
+      a.dk.h_last[i] = hs;
+      write_row<R, N>(a.dk.y_prev + (long)i * a.D, a.D, L.y, L.dim);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        R qm[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          R s2 = R(0);
+#pragma unroll
+          for (int j = 0; j < 7; ++j)
+            if (M::P[j][m] != 0.0) s2 += R(M::P[j][m]) * L.k[j][q];
+          qm[q] = hs * s2;
+        }
+        write_row<R, N>(a.dk.q + ((long)m * a.B + i) * a.D, a.D, qm, L.dim);
+      }
+    }
+    L.t = tnew;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      L.y[q] = Y[q];
+      L.k[0][q] = L.k[6][q];  // FSAL
+    }
+    L.err_prev = rmax(err, R(1e-4));
+    L.n_acc += 1;
+    L.prev_rej = 0;
+    if (last) L.status = kSuccess;
+  } else {
+    L.n_rej += 1;
+    L.prev_rej = 1;
+  }
+  L.h = hs * fac;
+  if (L.status == kRunning && !(double(L.h) > 16.0 * DBL_EPSILON * fabs(L.t)))
+    L.status = kDtUnderflow;
+}
+
+template <typename R>
+__device__ int fetch(const AnalyticArgs<R>& a, int kind) {
+  const int p = atomicAdd(&a.counts[2 + kind], 1);
+  const int n = __atomic_load_n(&a.counts[kind], __ATOMIC_RELAXED);
+  if (p >= n) return -1;
+  return kind == kKindVdp ? a.list[p] : a.list[a.B - 1 - p];
+}
+
+template <typename R, class M, class F>
+__global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
+                                                    int kind) {
+  Lane<R, F::N> L;
+  F f;
+  int inst = fetch(a, kind);
+  while (inst >= 0) {
+    if (a.st.status[inst] == kRunning) {
+      load_lane(a, inst, L);
+      f.load(a, inst, L.dim);
+      int used = 0;
+      while (L.status == kRunning && used < a.budget) {
+        attempt<R, M, F>(a, L, f);
+        ++used;
+      }
+      if (L.status == kRunning)
+        store_lane(a, L);
+      else
+        finish_lane(a, L);
+    }
+    inst = fetch(a, kind);
+  }
+}
+
+// ---- initialisation ----------------------------------------------------------
+
+template <typename R>
+__device__ bool instance_ok(const AnalyticArgs<R>& a, int i) {
+  const int kind = a.kind[i], dim = a.dim[i];
+  if (kind == kKindVdp) {
+    if (dim != 2 || a.D < 2 || a.mu == nullptr) return false;
+    if (!__builtin_isfinite(double(a.mu[i]))) return false;
+  } else if (kind == kKindLinear) {
+    if (dim < 1 || dim > 8 || dim > a.D || a.A == nullptr) return false;
+  } else {
+    return false;
+  }
+  const double t0 = a.t0[i], te = a.t_end[i];
+  if (!__builtin_isfinite(t0) || !__builtin_isfinite(te) || te < t0)
+    return false;
+  const double rt = a.rtol[i], at = a.atol[i];
+  if (!(rt >= 0.0) || !(at >= 0.0) || (rt == 0.0 && at == 0.0)) return false;
+  for (int q = 0; q < dim; ++q)
+    if (!__builtin_isfinite(double(a.y0[(long)i * a.D + q]))) return false;
+  double prev = t0;
+  for (int e = 0; e < a.E; ++e) {
+    const double v = a.t_eval[(long)i * a.E + e];
+    if (!(v >= prev && v <= te)) return false;
+    prev = v;
+  }
+  if (a.h0 != nullptr && !(a.h0[i] > 0.0)) return false;
+  return true;
+}
+
+// Hairer's starting step (Solving ODEs I, II.4) from f0 = f(t0, y0).
+template <typename R, class F>
+__device__ R start_step(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
+                        const F& f) {
+  constexpr int N = F::N;
+  const double span = L.te - L.t;
+  R sc[N], s0 = R(0), s1 = R(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    sc[q] = L.atol + rabs(L.y[q]) * L.rtol;
+    if (q < L.dim) {
+      const R u = L.y[q] / sc[q], v = L.k[0][q] / sc[q];
+      s0 += u * u;
+      s1 += v * v;
+    }
+  }
+  const R d0 = rsqrt_(s0 / R(L.dim)), d1 = rsqrt_(s1 / R(L.dim));
+  R h0 = (d0 < R(1e-5) || d1 < R(1e-5)) ? R(1e-6) : R(0.01) * d0 / d1;
+  h0 = rmin(h0, R(span));
+  R y1[N], f1[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) y1[q] = L.y[q] + h0 * L.k[0][q];
+  f(y1, f1);
+  L.n_fe += 1;
+  R s2 = R(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (q < L.dim) {
+      const R u = (f1[q] - L.k[0][q]) / sc[q];
+      s2 += u * u;
+    }
+  const R d2 = rsqrt_(s2 / R(L.dim)) / h0;
+  R h1;
+  if (d1 <= R(1e-15) && d2 <= R(1e-15))
+    h1 = rmax(R(1e-6), h0 * R(1e-3));
+  else
+    h1 = rpow(R(0.01) / rmax(d1, d2), R(0.2));
+  return rmin(rmin(R(100) * h0, h1), R(span));
+}
+
+template <typename R, class F>
+__device__ void init_one(const AnalyticArgs<R>& a, int i) {
+  constexpr int N = F::N;
+  Lane<R, N> L;
+  F f;
+  L.inst = i;
+  L.dim = a.dim[i];
+  f.load(a, i, L.dim);
+  L.t = a.t0[i];
+  L.te = a.t_end[i];
+  L.rtol = R(a.rtol[i]);
+  L.atol = R(a.atol[i]);
+  const R* y0 = a.y0 + (long)i * a.D;
+#pragma unroll
+  for (int q = 0; q < N; ++q) L.y[q] = q < L.dim ? y0[q] : R(0);
+  f(L.y, L.k[0]);
+  L.n_fe = 1;
+  L.n_att = L.n_acc = L.n_rej = 0;
+  L.prev_rej = 0;
+  L.err_prev = R(1);
+  L.cursor = 0;
+  while (L.cursor < a.E && a.t_eval[(long)i * a.E + L.cursor] <= L.t) {
+    write_row<R, N>(a.y_eval + ((long)i * a.E + L.cursor) * a.D, a.D, L.y,
+                    L.dim);
+    L.cursor += 1;
+  }
+  L.h = R(0);
+  if (L.te == L.t) {
+    L.status = kSuccess;
+    finish_lane(a, L);
+    return;
+  }
+  L.status = kRunning;
+  L.h = a.h0 != nullptr ? R(a.h0[i]) : start_step(a, L, f);
+  store_lane(a, L);
+  if (a.kind[i] == kKindVdp) {
+    const int p = atomicAdd(&a.counts[0], 1);
+    a.list[p] = i;
+  } else {
+    const int p = atomicAdd(&a.counts[1], 1);
+    a.list[a.B - 1 - p] = i;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void init_kernel(AnalyticArgs<R> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.B) return;
+  if (!instance_ok(a, i)) {
+    const State<R>& s = a.st;
+    s.status[i] = kInvalid;
+    s.n_att[i] = s.n_acc[i] = s.n_rej[i] = s.n_fe[i] = 0;
+    s.cursor[i] = 0;
+    s.t[i] = a.t0[i];
+    for (int q = 0; q < a.D; ++q) {
+      a.y_final[(long)i * a.D + q] = quiet_nan<R>();
+      s.y[(long)i * a.D + q] = quiet_nan<R>();
+    }
+    for (long e = 0; e < (long)a.E * a.D; ++e)
+      a.y_eval[(long)i * a.E * a.D + e] = quiet_nan<R>();
+    return;
+  }
+  if (a.kind[i] == kKindVdp)
+    init_one<R, VdpField<R>>(a, i);
+  else
+    init_one<R, LinearField<R>>(a, i);
+}
+
+// ---- dense output of the last accepted step ------------------------------------
+
+template <typename R>
+__global__ void dense_eval_kernel(DenseKeep<R> dk, State<R> st, int B, int D,
+                                  const double* t_query, R* y_out,
+                                  int32_t* qstatus) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const double tq = t_query[i];
+  const bool ok = st.n_acc[i] > 0 && tq >= dk.t_prev[i] && tq <= st.t[i];
+  qstatus[i] = ok ? 0 : 1;
+  const R th = ok ? R((tq - dk.t_prev[i]) / double(dk.h_last[i])) : R(0);
+  for (int q = 0; q < D; ++q) {
+    const long o = (long)i * D + q;
+    if (!ok) {
+      y_out[o] = quiet_nan<R>();
+      continue;
+    }
+    const long bd = (long)B * D;
+    const R v = dk.q[o] + th * (dk.q[bd + o] + th * (dk.q[2 * bd + o] +
+                                                      th * dk.q[3 * bd + o]));
+    y_out[o] = dk.y_prev[o] + th * v;
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---- launchers -----------------------------------------------------------------
+
+template <typename R>
+hipError_t launch_analytic_init(const AnalyticArgs<R>& a, int, hipStream_t s) {
+  const int block = 256;
+  const int grid = (a.B + block - 1) / block;
+  hipLaunchKernelGGL(init_kernel<R>, dim3(grid), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_analytic_solve(const AnalyticArgs<R>& a, int method,
+                                 int kind, int lanes, int block,
+                                 hipStream_t s) {
+  if (block <= 0) block = 64;
+  if (lanes <= 0) lanes = a.B;
+  const int grid = (lanes + block - 1) / block;
+  if (grid == 0) return hipSuccess;
+  if (kind == kKindVdp) {
+    if (method == 1)
+      hipLaunchKernelGGL((solve_kernel<R, Tsit5, VdpField<R>>), dim3(grid),
+                         dim3(block), 0, s, a, kind);
+    else
+      hipLaunchKernelGGL((solve_kernel<R, Dopri5, VdpField<R>>), dim3(grid),
+                         dim3(block), 0, s, a, kind);
+  } else {
+    if (method == 1)
+      hipLaunchKernelGGL((solve_kernel<R, Tsit5, LinearField<R>>), dim3(grid),
+                         dim3(block), 0, s, a, kind);
+    else
+      hipLaunchKernelGGL((solve_kernel<R, Dopri5, LinearField<R>>),
+                         dim3(grid), dim3(block), 0, s, a, kind);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dense_eval(const DenseKeep<R>& dk, const State<R>& st,
+                             int B, int D, const double* t_query, R* y_out,
+                             int32_t* qstatus, hipStream_t s) {
+  const int block = 256;
+  hipLaunchKernelGGL(dense_eval_kernel<R>, dim3((B + block - 1) / block),
+                     dim3(block), 0, s, dk, st, B, D, t_query, y_out, qstatus);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
+                     p, n, v);
+  return hipGetLastError();
+}
+
+template hipError_t launch_analytic_init<double>(const AnalyticArgs<double>&,
+                                                 int, hipStream_t);
+template hipError_t launch_analytic_init<float>(const AnalyticArgs<float>&,
+                                                int, hipStream_t);
+template hipError_t launch_analytic_solve<double>(const AnalyticArgs<double>&,
+                                                  int, int, int, int,
+                                                  hipStream_t);
+template hipError_t launch_analytic_solve<float>(const AnalyticArgs<float>&,
+                                                 int, int, int, int,
+                                                 hipStream_t);
+template hipError_t launch_dense_eval<double>(const DenseKeep<double>&,
+                                              const State<double>&, int, int,
+                                              const double*, double*,
+                                              int32_t*, hipStream_t);
+template hipError_t launch_dense_eval<float>(const DenseKeep<float>&,
+                                             const State<float>&, int, int,
+                                             const double*, float*, int32_t*,
+                                             hipStream_t);
+
+}  // namespace bode

@@ -1,0 +1,53 @@
+// Arguments of the analytic-field kernels (Van der Pol and linear instances).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace bode {
+
+template <typename R>
+struct AnalyticArgs {
+  int32_t B, D, E;
+  const R* y0;
+  const double* t0;
+  const double* t_end;
+  const double* rtol;
+  const double* atol;
+  const double* t_eval;
+  const double* h0;
+  const int32_t* kind;
+  const int32_t* dim;
+  const R* mu;
+  const R* A;
+  R* y_eval;
+  R* y_final;
+  State<R> st;
+  // Work queue: instances still running after initialisation, Van der Pol
+  // ones from the front of `list`, linear ones from the back.
+  // counts = {n_vdp, n_linear, head_vdp, head_linear}.
+  int32_t* list;
+  int32_t* counts;
+  double* h_rec;  // [B, rec_cap] attempted step sizes (rejected < 0)
+  int32_t rec_cap;
+  DenseKeep<R> dk;
+  int32_t keep_dense;
+  Ctrl ctrl;
+  int32_t budget;  // attempts per instance in one solve call
+};
+
+template <typename R>
+hipError_t launch_analytic_init(const AnalyticArgs<R>& a, int method,
+                                hipStream_t s);
+template <typename R>
+hipError_t launch_analytic_solve(const AnalyticArgs<R>& a, int method,
+                                 int kind, int lanes, int block,
+                                 hipStream_t s);
+template <typename R>
+hipError_t launch_dense_eval(const DenseKeep<R>& dk, const State<R>& st,
+                             int B, int D, const double* t_query, R* y_out,
+                             int32_t* qstatus, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
+
+}  // namespace bode

@@ -1,0 +1,52 @@
+// Batched ("modular") solver for neural right-hand sides: the state lives in
+// HBM as [B, D] arrays and each step is a short sequence of kernels (stage
+// combination fused into the MLP GEMM prologue, the error norm + controller +
+// commit + dense output), replayed from a captured HIP graph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/batchode.h"
+
+namespace bode {
+
+struct ModularPlan {
+  bode_config cfg{};
+  bode_problem p{};
+  // per-instance state [B]
+  double* t = nullptr;
+  void* h = nullptr;
+  void* err_prev = nullptr;
+  int32_t *n_att = nullptr, *n_acc = nullptr, *n_rej = nullptr,
+          *n_fe = nullptr, *status = nullptr, *cursor = nullptr,
+          *prev_rej = nullptr;
+  double* h_rec = nullptr;
+  void* impl = nullptr;  // kernel-side plan (owned)
+};
+
+size_t modular_layout(const bode_config& c, void* base, ModularPlan* mp);
+std::string modular_supported(const bode_config& c);
+hipError_t modular_init(ModularPlan& mp, const bode_config& c,
+                        const bode_problem& p, hipStream_t s);
+hipError_t modular_run(ModularPlan& mp, int budget, hipStream_t s);
+hipError_t modular_eval(ModularPlan& mp, const double* t_query, void* y_out,
+                        int32_t* qstatus, hipStream_t s);
+hipError_t modular_backward(ModularPlan& mp, const void* g_y_eval,
+                            const void* g_y_final, void* dy0, void* dtheta,
+                            hipStream_t s);
+void modular_release(ModularPlan& mp);
+
+hipError_t launch_count_equal(const int32_t* a, int n, int32_t v, int32_t* out,
+                              hipStream_t s);
+
+// Launch-shape tuning shared by the solver handle and the autotuner.
+void set_tune(const bode_config& c, int block, int lanes_vdp, int lanes_lin,
+              int row_tile);
+int get_row_tile(const bode_config& c);
+void set_thread_error(const std::string& m);
+int autotune(const bode_config* cfg, const bode_problem* p, void* workspace,
+             size_t workspace_bytes, void* stream);
+
+}  // namespace bode

@@ -1,0 +1,253 @@
+"""Shared helpers of the GPU parity tests (they call the HIP path only
+through the C ABI, via paper_2210_12375_amd.binding)."""
+import numpy as np
+
+import oracle
+from paper_2210_12375_amd import binding as bd
+from paper_2210_12375_amd import workloads as W
+
+# FP64 mode must match the FP64 oracle to this relative error per instance
+# with identical accepted / rejected counts.
+TOL_FP64 = 1e-9
+# FP32 state (and the FP32 controller): the oracle replays the GPU's accepted
+# steps in FP64; per-instance relative error bound.
+TOL_FP32 = 1e-4
+# BF16 MFMA right-hand side, same replay.
+TOL_BF16 = 1e-2
+
+
+def per_instance_absdiff(a_eval, a_final, b_eval, b_final):
+    """(max |a - b|, max |b|) per instance over evaluation outputs and final
+    state."""
+    B = a_final.shape[0]
+    a = np.concatenate([a_eval.reshape(B, -1), a_final.reshape(B, -1)], axis=1)
+    b = np.concatenate([b_eval.reshape(B, -1), b_final.reshape(B, -1)], axis=1)
+    nan_a, nan_b = np.isnan(a), np.isnan(b)
+    assert np.array_equal(nan_a, nan_b), "NaN pattern differs"
+    a = np.where(nan_a, 0.0, a)
+    b = np.where(nan_b, 0.0, b)
+    return np.abs(a - b).max(axis=1), np.abs(b).max(axis=1)
+
+
+def per_instance_rel(a_eval, a_final, b_eval, b_final):
+    """max |a - b| / max |b| per instance over evaluation outputs and final
+    state (robust at zero crossings of single components)."""
+    B = a_final.shape[0]
+    a = np.concatenate([a_eval.reshape(B, -1), a_final.reshape(B, -1)], axis=1)
+    b = np.concatenate([b_eval.reshape(B, -1), b_final.reshape(B, -1)], axis=1)
+    nan_a, nan_b = np.isnan(a), np.isnan(b)
+    assert np.array_equal(nan_a, nan_b), "NaN pattern differs"
+    a = np.where(nan_a, 0.0, a)
+    b = np.where(nan_b, 0.0, b)
+    scale = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return np.abs(a - b).max(axis=1) / scale
+
+
+def run_gpu(p, method="dopri5", precision="fp64", rhs=bd.RHS_ANALYTIC, **kw):
+    import torch
+    dp = bd.device_problem(p, precision)
+    s = bd.Solver(dp, method=method, precision=precision, rhs=rhs, **kw)
+    s.solve()
+    st = s.stats()
+    out = dict(y_eval=s.y_eval.double().cpu().numpy(),
+               y_final=s.y_final.double().cpu().numpy(),
+               **{k: v.cpu().numpy() for k, v in st.items()})
+    if s.cfg.record_cap > 0:
+        h, n = s.steps()
+        out["h_rec"] = h.cpu().numpy()
+        out["n_rec"] = n.cpu().numpy()
+    torch.cuda.synchronize()
+    return out, s
+
+
+def controller(ctrl):
+    return bd.I_CONTROLLER if ctrl == "I" else bd.PI_CONTROLLER
+
+
+def assert_fp64_parity(g, r, max_mismatch=0):
+    """Identical counters and statuses, outputs within TOL_FP64.  Instances
+    whose step sequence split at a near-tie accept decision (error norm within
+    rounding of 1) are allowed up to max_mismatch, and must still agree to the
+    tolerance level of the solve."""
+    same = ((g["n_accepted"] == r["n_accepted"])
+            & (g["n_rejected"] == r["n_rejected"]))
+    np.testing.assert_array_equal(g["status"], r["status"])
+    bad = np.flatnonzero(~same)
+    assert bad.size <= max_mismatch, (bad, g["n_accepted"][bad],
+                                      r["n_accepted"][bad])
+    rel = per_instance_rel(g["y_eval"], g["y_final"], r["y_eval"], r["y_final"])
+    ok = np.flatnonzero(same)
+    assert rel[ok].max(initial=0.0) <= TOL_FP64, (rel[ok].max(),
+                                                  ok[np.argmax(rel[ok])])
+    if bad.size:
+        assert rel[bad].max() <= 1e-4, rel[bad]
+    np.testing.assert_array_equal(g["n_feval"][ok], r["n_feval"][ok])
+    return rel
+
+
+def oracle_replay(p, g, method):
+    """The oracle's FP64 replay of the GPU's accepted step sequence."""
+    n = g["n_rec"]
+    cap = int(n.max()) if n.size else 0
+    assert cap <= g["h_rec"].shape[1], "record_cap too small for the replay"
+    return oracle.solve(p, method=method, h_replay=g["h_rec"][:, :max(cap, 1)],
+                        n_replay=n)
+
+
+def conditioned_counts(p, method, ctrl=None, eps=1e-12):
+    """The oracle's solve plus a mask of instances whose accepted / rejected
+    counts are a well-conditioned function of the input: unchanged when
+    rtol and atol are scaled by 1 +- eps.  Instances whose step size sits at
+    the stability boundary (the linear family at h * lambda_max ~ 3.3) flip
+    accept decisions under any 1-ulp perturbation, including the oracle's own
+    compilation with or without fused multiply-add, so only their solutions,
+    not their exact step counts, are defined.  The probes: tolerances scaled
+    by 1 +- eps, and the oracle's source compiled with contracted
+    multiply-adds."""
+    kw = ctrl or {}
+    r0 = oracle.solve(p, method=method, **kw)
+    ok = np.ones(p["y0"].shape[0], bool)
+    probes = [(dict(p, rtol=p["rtol"] * s, atol=p["atol"] * s), None)
+              for s in (1 + eps, 1 - eps)] + [(p, "fma")]
+    for q, variant in probes:
+        r = oracle.solve(q, method=method, variant=variant, **kw)
+        ok &= ((r["n_accepted"] == r0["n_accepted"])
+               & (r["n_rejected"] == r0["n_rejected"]))
+    return r0, ok
+
+
+def replay_check(p, g, method, ctrl=None, tol=TOL_FP64, decisions=True,
+                 decision_kinds=(0, 1)):
+    """Decision-by-decision check of the GPU's attempt record (every attempted
+    step size, negated when rejected) against the FP64 oracle:
+      - replaying exactly that sequence reproduces every output within tol;
+      - the first attempt is Hairer's starting step (clipped to the span);
+      - every accept / reject decision agrees with the oracle's FP64 error
+        test, except near-ties |err - 1| < 1e-4;
+      - every later attempt's size is the oracle controller's proposal from
+        the replayed history (or the clip to t_end), within 1e-4 (the error
+        estimate of a tiny step carries ~1e-5 relative rounding noise).
+    Every valid instance is replayed (those that stopped early, e.g. at
+    max_steps, without the final clip to t_end); decisions and
+    proposals are checked for the kinds in decision_kinds (at the stability
+    boundary the linear family's error norm is rounding noise at the atol
+    level, so its decisions are not defined beyond that noise)."""
+    kw = ctrl or {}
+    n = g["n_rec"]
+    H = g["h_rec"]
+    assert n.max() <= H.shape[1], "record_cap too small"
+    idx = np.flatnonzero((g["status"] != 4) & (n > 0))
+    q = W.subset(p, idx)
+    cap = int(max(1, n[idx].max()))
+    Hs = H[idx, :cap]
+    fin = (g["status"][idx] == 1).astype(np.int32)
+    rr = oracle.solve(q, method=method, h_replay=Hs, n_replay=n[idx],
+                      replay_errors=True, replay_final=fin, **kw)
+    np.testing.assert_array_equal(rr["status"] == 1, fin == 1)
+    # the instance's own rounding sensitivity on this step sequence: the same
+    # replay by the oracle's source compiled with contracted multiply-adds
+    rf = oracle.solve(q, method=method, h_replay=Hs, n_replay=n[idx],
+                      variant="fma", replay_errors=True, replay_final=fin,
+                      **kw)
+    sens, _ = per_instance_absdiff(rf["y_eval"], rf["y_final"], rr["y_eval"],
+                                   rr["y_final"])
+    diff, scale = per_instance_absdiff(g["y_eval"][idx], g["y_final"][idx],
+                                       rr["y_eval"], rr["y_final"])
+    allowed = np.maximum(tol * scale, 1000.0 * sens)
+    worst = np.argmax(diff / np.maximum(allowed, 1e-300))
+    assert np.all(diff <= allowed), (idx[worst], diff[worst], scale[worst],
+                                     sens[worst])
+    rel = diff / np.maximum(scale, 1e-300)
+    if not decisions:
+        return rel
+    valid = np.arange(cap)[None, :] < n[idx][:, None]
+    err = rr["err_rec"]
+    acc = Hs > 0
+    # a decision is a near-tie when err sits within its own rounding noise of
+    # 1: the embedded estimate cancels (sum e_j = 0), so on very small steps
+    # it carries relative noise up to ~1e-5; also ten times the norm's change
+    # under contracted multiply-adds
+    err_sens = np.abs(err - rf["err_rec"])
+    tie = np.abs(err - 1.0) < np.maximum(1e-4, 10.0 * err_sens)
+    dk = np.isin(q["kind"], decision_kinds)[:, None]
+    wrong = valid & dk & (acc != (err < 1.0)) & ~tie
+    assert not wrong.any(), (np.argwhere(wrong)[:5], err[wrong][:5])
+    # start times of every attempt (sequential sums, as the kernel forms t)
+    hacc = np.where(acc & valid, np.abs(Hs), 0.0)
+    t_start = np.empty_like(Hs)
+    t = q["t0"].astype(np.float64).copy()
+    for k in range(cap):
+        t_start[:, k] = t
+        t = t + hacc[:, k]
+    te = q["t_end"][:, None]
+    prop = rr["hprop_rec"][:, :-1]
+    prop_sens = np.abs(prop - rf["hprop_rec"][:, :-1])
+    nxt = np.abs(Hs[:, 1:])
+    ts = t_start[:, 1:]
+    clip = ts + prop >= te
+    expect = np.where(clip, te - ts, prop)
+    ambiguous = np.abs(ts + prop - te) <= 1e-6 * prop
+    chk = valid[:, 1:] & ~ambiguous & dk
+    bad = chk & (np.abs(nxt - expect)
+                 > np.maximum(1e-4 * expect, 10.0 * prop_sens))
+    assert not bad.any(), (np.argwhere(bad)[:5], nxt[bad][:5], expect[bad][:5])
+    if q.get("h0") is None:
+        for j in range(min(len(idx), 64)):
+            if q["t_end"][j] == q["t0"][j]:
+                continue
+            h0, _ = oracle.initial_step(q, j)
+            assert abs(abs(Hs[j, 0]) - h0) <= 1e-9 * h0, (j, Hs[j, 0], h0)
+    return rel
+
+
+def free_check(p, g, method, ctrl=None, exact_kinds=(0,), loose=1e-4,
+               mismatch_frac=0.005):
+    """The GPU's free-running solve against the oracle's: identical statuses;
+    identical counts for well-conditioned instances of exact_kinds (a
+    near-tie share of mismatch_frac allowed); counts within 5 % (or 3) for
+    the rest; outputs within `loose` (both are valid solutions at the stated
+    tolerance once their step sequences have parted).  The linear family is
+    not in exact_kinds: its steps settle on the method's stability boundary
+    (h * lambda_max ~ 3.3 for Dormand-Prince) where any rounding change flips
+    accept decisions, so its exact counts are not defined."""
+    r0, ok = conditioned_counts(p, method, ctrl)
+    ok &= np.isin(p["kind"], exact_kinds)
+    np.testing.assert_array_equal(g["status"], r0["status"])
+    same = ((g["n_accepted"] == r0["n_accepted"])
+            & (g["n_rejected"] == r0["n_rejected"]))
+    cond = np.flatnonzero(ok)
+    bad = cond[~same[cond]]
+    assert bad.size <= max(1, int(mismatch_frac * cond.size)), bad
+    ill = np.flatnonzero(~ok)
+    d = np.abs(g["n_accepted"][ill] - r0["n_accepted"][ill])
+    assert np.all(d <= np.maximum(3, 0.05 * r0["n_accepted"][ill])), d.max()
+    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"],
+                                       r0["y_eval"], r0["y_final"])
+    # decayed instances are atol-level noise: an absolute floor of 100 atol
+    allowed = loose * scale + 100.0 * p["atol"]
+    worst = np.argmax(diff / allowed)
+    assert np.all(diff <= allowed), (worst, diff[worst], scale[worst])
+    return dict(n_exact=cond.size, n_mismatch=bad.size, n_ill=ill.size,
+                max_rel=float((diff / np.maximum(scale, 1e-300)).max()))
+
+
+def assert_uneven_parity(p, g, method, ctrl=None):
+    rel = replay_check(p, g, method, ctrl, decision_kinds=(0,))
+    info = free_check(p, g, method, ctrl)
+    info["replay_max_rel"] = float(rel.max(initial=0.0))
+    return info
+
+
+def assert_linear_accuracy(p, g, n_max=64, factor=50.0):
+    """Linear instances against the matrix exponential at every output."""
+    from scipy.linalg import expm
+    lin = np.flatnonzero(p["kind"] == 1)[:n_max]
+    for i in lin:
+        A = p["A"][i]
+        for e in range(p["t_eval"].shape[1]):
+            ref = expm(A * (p["t_eval"][i, e] - p["t0"][i])) @ p["y0"][i]
+            bound = factor * (p["rtol"][i] * np.abs(ref).max() + p["atol"][i])
+            assert np.abs(g["y_eval"][i, e] - ref).max() <= bound, (i, e)
+        ref = expm(A * (p["t_end"][i] - p["t0"][i])) @ p["y0"][i]
+        bound = factor * (p["rtol"][i] * np.abs(ref).max() + p["atol"][i])
+        assert np.abs(g["y_final"][i] - ref).max() <= bound, i

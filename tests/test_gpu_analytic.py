@@ -1,0 +1,226 @@
+"""GPU parity of the analytic-field path (Van der Pol / linear batches)
+against the FP64 oracle, through the C ABI.
+
+FP64 mode: identical per-instance accepted / rejected / evaluation counts and
+statuses, outputs within 1e-9 relative per instance.  FP32 mode: the oracle
+replays the GPU's accepted steps in FP64, outputs within 1e-4 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import (TOL_FP32, assert_fp64_parity, assert_linear_accuracy,
+                         assert_uneven_parity, controller, oracle_replay,
+                         per_instance_absdiff, per_instance_rel, replay_check,
+                         run_gpu)
+from paper_2210_12375_amd import binding as bd
+from paper_2210_12375_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+METHODS = ["dopri5", "tsit5"]
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("ctrl", ["PI", "I"])
+def test_vdp64_fp64_parity(method, ctrl):
+    flush(f"vdp64 fp64 {method} {ctrl}")
+    p = W.vdp_batch()
+    g, _ = run_gpu(p, method=method, **controller(ctrl))
+    r = oracle.solve(p, method=method, **controller(ctrl))
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("ctrl", ["PI", "I"])
+def test_uneven_short_horizon_exact(method, ctrl):
+    """The uneven batch over short horizons (t_end / 12.5), where every step
+    is accuracy-limited: identical counts and statuses for every instance,
+    outputs within 1e-9, and every decision and step-size proposal of the
+    GPU's attempt record equal to the oracle's."""
+    flush(f"uneven short fp64 {method} {ctrl}")
+    p = W.uneven_batch(B=2000)
+    p["t_end"] = p["t_end"] / 12.5
+    p["t_eval"] = p["t_eval"] / 12.5
+    c = controller(ctrl)
+    g, _ = run_gpu(p, method=method, record_cap=2048, **c)
+    r = oracle.solve(p, method=method, **c)
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
+    replay_check(p, g, method, c)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_uneven_fp64_parity_ragged(method):
+    """Mixed Van der Pol (D=2 in an 8-wide row) and linear instances over the
+    full horizons, some linear ones with a smaller true dimension; B not a
+    multiple of 64."""
+    flush(f"uneven fp64 {method}")
+    p = W.uneven_batch(B=1500)
+    lin = np.flatnonzero(p["kind"] == W.LINEAR)
+    for j, i in enumerate(lin[:40]):
+        d = 1 + j % 7
+        p["dim"][i] = d
+        p["A"][i, d:, :] = 0.0
+        p["A"][i, :, d:] = 0.0
+        p["y0"][i, d:] = 0.0
+    g, _ = run_gpu(p, method=method, record_cap=4096)
+    info = assert_uneven_parity(p, g, method)
+    flush(f"  {info}")
+    assert_linear_accuracy(p, g)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_uneven_fp32_replay_parity(method):
+    flush(f"uneven fp32 replay {method}")
+    p = W.uneven_batch(B=1024)
+    g, _ = run_gpu(p, method=method, precision="fp32", record_cap=4096)
+    assert np.all(g["status"] == bd.SUCCESS)
+    r = oracle_replay(p, g, method)
+    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
+                                       r["y_final"])
+    # relative to the instance's scale: its outputs or, for instances that
+    # decay far below their start, its initial state
+    scale = np.maximum(scale, np.abs(p["y0"]).max(axis=1))
+    rel = diff / scale
+    assert rel.max() <= TOL_FP32, (rel.max(), np.argmax(rel))
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_full_uneven_batch_sampled(method):
+    """The full 65,536-instance uneven batch in the benchmark's launch
+    configuration; 384 sampled instances checked against the oracle."""
+    flush(f"uneven full 65536 fp64 {method}")
+    p = W.uneven_batch()
+    g, _ = run_gpu(p, method=method, record_cap=2048)
+    assert np.all(g["status"] == bd.SUCCESS)
+    idx = np.random.default_rng(99).choice(p["y0"].shape[0], 384, replace=False)
+    q = W.subset(p, idx)
+    gs = {k: v[idx] for k, v in g.items()}
+    info = assert_uneven_parity(q, gs, method)
+    flush(f"  {info}")
+    # whole-batch invariants hold at any size
+    np.testing.assert_array_equal(g["n_attempted"],
+                                  g["n_accepted"] + g["n_rejected"])
+    np.testing.assert_array_equal(g["n_feval"], 2 + 6 * g["n_attempted"])
+    assert np.isfinite(g["y_eval"]).all()
+
+
+def test_step_calls_match_one_solve():
+    """solver_step in slices of 7 attempts gives bitwise the same result as a
+    single solver_solve, and reports the running count."""
+    flush("step slices")
+    p = W.uneven_batch(B=700)
+    g, _ = run_gpu(p, method="tsit5")
+    dp = bd.device_problem(p, "fp64")
+    s = bd.Solver(dp, method="tsit5")
+    running = []
+    for _ in range(10000):
+        n = s.step(7, want_running=True)
+        running.append(n)
+        if n == 0:
+            break
+    assert running[-1] == 0 and running[0] > 0
+    assert all(a >= b for a, b in zip(running, running[1:]))
+    np.testing.assert_array_equal(s.y_final.cpu().numpy(), g["y_final"])
+    np.testing.assert_array_equal(s.y_eval.cpu().numpy(), g["y_eval"])
+    st = s.stats()
+    np.testing.assert_array_equal(st["n_accepted"].cpu().numpy(),
+                                  g["n_accepted"])
+
+
+def test_eval_last_step_dense_output():
+    """solver_eval answers inside each instance's last accepted step with the
+    same interpolant the oracle uses."""
+    flush("solver_eval")
+    p = W.vdp_batch(B=100)
+    B = 100
+    dp = bd.device_problem(p, "fp64")
+    s = bd.Solver(dp, method="dopri5", keep_dense=1, record_cap=2048)
+    s.step(20)
+    h, n = s.steps()
+    h = h.cpu().numpy()
+    n = n.cpu().numpy()
+    hacc, nacc = oracle.accepted_steps(h, n)
+    t_prev = np.zeros(B)
+    for i in range(B):  # sequential sums, as the kernel advances t
+        t = p["t0"][i]
+        for k in range(nacc[i] - 1):
+            t = t + hacc[i, k]
+        t_prev[i] = t
+    t_cur = t_prev + hacc[np.arange(B), nacc - 1]
+    tq = t_prev + 0.37 * (t_cur - t_prev)
+    y, q = s.eval(torch.as_tensor(tq, device="cuda"))
+    y = y.cpu().numpy()
+    assert np.all(q.cpu().numpy() == 0)
+    # oracle: replay the same steps with tq as the single evaluation time
+    r = oracle.solve(dict(p, t_eval=tq[:, None]), method="dopri5",
+                     h_replay=h[:, :n.max()], n_replay=n)
+    err = np.abs(y - r["y_eval"][:, 0]).max(axis=1) / np.abs(r["y_eval"][:, 0]).max(axis=1)
+    assert err.max() < 1e-9
+    # outside the last step: flagged and NaN
+    y2, q2 = s.eval(torch.as_tensor(t_prev - 1.0, device="cuda"))
+    assert np.all(q2.cpu().numpy() == 1) and np.isnan(y2.cpu().numpy()).all()
+
+
+def test_edge_cases():
+    flush("edge cases")
+    p = W.uneven_batch(B=130)
+    p["t_end"][3] = p["t0"][3]
+    p["t_eval"][3] = 0.0
+    p["t_eval"][5, 0] = 0.0            # evaluation at t0
+    p["t_eval"][6, -1] = p["t_end"][6]  # evaluation at t_end
+    p["t_eval"][7, 4] = -1.0           # invalid: before t0 -> INVALID
+    p["rtol"][8] = 0.0
+    p["atol"][8] = 0.0                 # invalid tolerances
+    p["y0"][9, 0] = np.nan             # invalid state
+    g, _ = run_gpu(p, method="dopri5", record_cap=4096)
+    r = oracle.solve(p, method="dopri5")
+    np.testing.assert_array_equal(g["status"], r["status"])
+    assert list(g["status"][[3, 7, 8, 9]]) == [1, 4, 4, 4]
+    ok = r["status"] != bd.INVALID
+    sub = {k: v[ok] for k, v in g.items()}
+    assert_uneven_parity(W.subset(p, np.flatnonzero(ok)), sub, "dopri5")
+    assert np.isnan(g["y_final"][7, :2]).all()
+    # max_steps: every instance stops after 3 attempts
+    g, _ = run_gpu(p, method="tsit5", max_steps=3, record_cap=8)
+    r = oracle.solve(p, method="tsit5", max_steps=3)
+    np.testing.assert_array_equal(g["status"], r["status"])
+    running = r["status"] == bd.MAX_STEPS
+    assert running.sum() > 100
+    np.testing.assert_array_equal(g["n_attempted"][running], 3)
+    np.testing.assert_array_equal(g["n_accepted"], r["n_accepted"])
+    sub = {k: v[ok] for k, v in g.items()}
+    replay_check(W.subset(p, np.flatnonzero(ok)), sub, "tsit5")
+
+
+def test_single_instance_and_user_h0():
+    flush("single instance, h0")
+    p = W.subset(W.vdp_batch(), [5])
+    p["h0"] = np.array([1e-3])
+    g, _ = run_gpu(p, method="dopri5")
+    r = oracle.solve(p, method="dopri5")
+    assert_fp64_parity(g, r)
+    assert g["n_feval"][0] == 1 + 6 * g["n_attempted"][0]
+
+
+def test_autotune_keeps_results():
+    flush("autotune")
+    p = W.uneven_batch(B=4096)
+    dp = bd.device_problem(p, "fp32")
+    s = bd.Solver(dp, method="dopri5", precision="fp32")
+    bd.solver_autotune(s.cfg, s.prob, s.workspace.data_ptr(),
+                       s.workspace.numel(), s.stream.cuda_stream)
+    torch.cuda.synchronize()
+    s.close()
+    g1, _ = run_gpu(p, method="dopri5", precision="fp32")
+    g2, _ = run_gpu(p, method="dopri5", precision="fp32", tune_block=64,
+                    tune_lanes=4096)
+    np.testing.assert_array_equal(g1["y_final"], g2["y_final"])
+    np.testing.assert_array_equal(g1["n_accepted"], g2["n_accepted"])

@@ -92,8 +92,7 @@ def perturb_mlp(p, w, s):
 def check_adjoint(p, method, with_theta, rng, n_dirs=3):
     r = oracle.solve(p, method=method, record_cap=512)
     assert np.all(r["status"] == 1)
-    cap = int(r["n_accepted"].max())
-    h, n = r["h_rec"][:, :cap], r["n_accepted"]
+    h, n = oracle.accepted_steps(r["h_rec"], r["n_attempted"])
     B, D = p["y0"].shape
     E = p["t_eval"].shape[1] if p.get("t_eval") is not None else 0
     g_eval = rng.standard_normal((B, E, D))

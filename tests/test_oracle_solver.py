@@ -199,6 +199,7 @@ def test_matches_scipy_rk45_step_for_step():
     rejected step counts, step sizes, final states and dense outputs."""
     p = W.vdp_batch(B=16)
     r = oracle.solve(p, method="dopri5", record_cap=4000, **I_CONTROLLER)
+    hacc, _ = oracle.accepted_steps(r["h_rec"], r["n_attempted"])
     for i in range(16):
         mu = p["mu"][i]
         f = lambda t, y: np.array([y[1], mu * (1 - y[0] ** 2) * y[1] - y[0]])
@@ -209,8 +210,7 @@ def test_matches_scipy_rk45_step_for_step():
         assert r["n_accepted"][i] == n_acc
         assert r["n_rejected"][i] == n_att - n_acc
         assert r["n_feval"][i] == s.nfev
-        np.testing.assert_allclose(r["h_rec"][i, :n_acc], np.diff(s.t),
-                                   rtol=1e-6)
+        np.testing.assert_allclose(hacc[i, :n_acc], np.diff(s.t), rtol=1e-6)
         scale = np.abs(s.y).max()
         assert np.abs(r["y_final"][i] - s.y[:, -1]).max() < 1e-9 * scale
         ye = s.sol(p["t_eval"][i]).T
@@ -243,8 +243,8 @@ def test_controller_steady_state(ctrl, beta):
              y0=np.ones((1, 1)), t0=np.zeros(1), t_end=np.full(1, 40.0),
              rtol=np.full(1, 1e-6), atol=np.zeros(1), A=-np.ones((1, 1, 1)))
     r = oracle.solve(p, method="dopri5", beta1=b1, beta2=b2, record_cap=4000)
-    n = r["n_accepted"][0]
-    h = r["h_rec"][0, n - 5]  # well before the clipped last step
+    hacc, nacc = oracle.accepted_steps(r["h_rec"], r["n_attempted"])
+    h = hacc[0, nacc[0] - 5]  # well before the clipped last step
     c, A, b, bh = oracle.tableau("dopri5")
     z = -h
     stage = np.linalg.solve(np.eye(7) - z * A, np.ones(7))  # k_j / (lam y_n)
@@ -263,7 +263,8 @@ def test_constant_field_grows_steps_by_fac_max():
     assert np.all(r["status"] == 1)
     ref = p["y0"] + p["mlp"]["b3"][None, :] * 1.0
     np.testing.assert_allclose(r["y_final"], ref, rtol=1e-14, atol=1e-14)
-    h = r["h_rec"][0, :r["n_accepted"][0]]
+    hacc, nacc = oracle.accepted_steps(r["h_rec"], r["n_attempted"])
+    h = hacc[0, :nacc[0]]
     np.testing.assert_allclose(h[1:3] / h[:2], 10.0, rtol=1e-12)
 
 
@@ -337,8 +338,18 @@ def test_instances_are_independent():
 def test_replay_reproduces_the_adaptive_solve():
     p = W.uneven_batch(B=32)
     r = oracle.solve(p, method="dopri5", record_cap=4000)
-    cap = int(r["n_accepted"].max())
+    cap = int(r["n_attempted"].max())
     q = oracle.solve(p, method="dopri5", h_replay=r["h_rec"][:, :cap],
-                     n_replay=r["n_accepted"])
+                     n_replay=r["n_attempted"], replay_errors=True)
     np.testing.assert_array_equal(q["y_final"], r["y_final"])
     np.testing.assert_array_equal(q["y_eval"], r["y_eval"])
+    # replaying the signed attempt record reproduces every decision: the
+    # accepted attempts had err < 1, the rejected ones err >= 1, and each
+    # attempt's size is the previous attempt's proposal (or the end clip)
+    valid = np.arange(cap)[None, :] < r["n_attempted"][:, None]
+    acc = r["h_rec"][:, :cap] > 0
+    np.testing.assert_array_equal((q["err_rec"] < 1)[valid], acc[valid])
+    prop = q["hprop_rec"][:, :-1]
+    nxt = np.abs(r["h_rec"][:, 1:cap])
+    ok = valid[:, 1:] & (nxt < prop * (1 - 1e-12))  # clipped final steps
+    assert np.all((np.abs(nxt - prop) <= 1e-15 * prop)[valid[:, 1:] & ~ok])
