@@ -38,7 +38,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), "
+                         "the reference kernel for HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4,
+                      "copy_calibration_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
 
 
 def ensure_built():
@@ -113,6 +129,32 @@ def error_at_tolerance(p, y_eval, y_final, ref, idx):
     return float(np.median(e)), float(e.max())
 
 
+PROFILE = os.path.join(ROOT, "profiles",
+                       "analytic_persistent_uneven65536_fp32.md")
+KERNEL_SOURCES = ["analytic.hip", "common.hpp", "tableau.hpp", "analytic.hpp"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent solve from the committed
+    rocprofv3 counter summary, or None if the kernel sources changed since
+    the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(l.split(": ", 1) for l in text.splitlines()
+                  if ": " in l and l.split(": ", 1)[0].isidentifier())
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2210_12375_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(fields["traffic_bytes_per_launch_pair"])
+
+
 def cpu_baseline(p, method, seconds):
     """The FP64 oracle on the host cores over whole copies of a bounded
     sample of the same batch."""
@@ -151,6 +193,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(3)
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     ensure_built()
     from paper_2210_12375_amd import binding as bd
     from paper_2210_12375_amd import roofline as rl
@@ -226,7 +271,9 @@ def main():
                                                   "lanes"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
+                     "traffic": (measured_traffic()
+                                 if (a.method, a.precision) == ("dopri5", "fp32")
+                                 else None),
                      "kernel": "persistent solve (Van der Pol + linear "
                                "kernels, concurrent)",
                      "critical_path_steps": head["steps_max"]},

@@ -32,9 +32,11 @@ template <typename R>
 struct VdpField {
   static constexpr int N = 2;
   R mu;
-  __device__ void load(const AnalyticArgs<R>& a, int i, int) { mu = a.mu[i]; }
+  __device__ __forceinline__ void load(const AnalyticArgs<R>& a, int i, int) {
+    mu = a.mu[i];
+  }
   // x' = v, v' = mu (1 - x^2) v - x
-  __device__ void operator()(const R* y, R* out) const {
+  __device__ __forceinline__ void operator()(const R* y, R* out) const {
     const R x = y[0], v = y[1];
     out[0] = v;
     out[1] = mu * (R(1) - x * x) * v - x;
@@ -45,7 +47,7 @@ template <typename R>
 struct LinearField {
   static constexpr int N = 8;
   R A[8][8];
-  __device__ void load(const AnalyticArgs<R>& a, int i, int dim) {
+  __device__ __forceinline__ void load(const AnalyticArgs<R>& a, int i, int dim) {
     const R* Ai = a.A + (long)i * a.D * a.D;
 #pragma unroll
     for (int r = 0; r < 8; ++r)
@@ -53,7 +55,7 @@ struct LinearField {
       for (int c = 0; c < 8; ++c)
         A[r][c] = (r < dim && c < dim) ? Ai[(long)r * a.D + c] : R(0);
   }
-  __device__ void operator()(const R* y, R* out) const {
+  __device__ __forceinline__ void operator()(const R* y, R* out) const {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       R acc = R(0);
@@ -83,7 +85,7 @@ struct Lane {
 };
 
 template <typename R, int N>
-__device__ void write_row(R* row, int D, const R* v, int dim) {
+__device__ __forceinline__ void write_row(R* row, int D, const R* v, int dim) {
 #pragma unroll
   for (int q = 0; q < N; ++q)
     if (q < D) row[q] = q < dim ? v[q] : R(0);
@@ -91,12 +93,12 @@ __device__ void write_row(R* row, int D, const R* v, int dim) {
 }
 
 template <typename R, int N>
-__device__ void fill_nan_row(R* row, int D, int dim) {
+__device__ __forceinline__ void fill_nan_row(R* row, int D, int dim) {
   for (int q = 0; q < D; ++q) row[q] = q < dim ? quiet_nan<R>() : R(0);
 }
 
 template <typename R, int N>
-__device__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<R, N>& L) {
+__device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<R, N>& L) {
   const State<R>& s = a.st;
   L.inst = i;
   L.dim = a.dim[i];
@@ -124,7 +126,7 @@ __device__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<R, N>& L) {
 }
 
 template <typename R, int N>
-__device__ void store_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
+__device__ __forceinline__ void store_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
   const State<R>& s = a.st;
   const int i = L.inst;
   s.t[i] = L.t;
@@ -143,7 +145,7 @@ __device__ void store_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
 
 // Writes the final state, and NaN for evaluation times never reached.
 template <typename R, int N>
-__device__ void finish_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
+__device__ __forceinline__ void finish_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
   store_lane(a, L);
   write_row<R, N>(a.y_final + (long)L.inst * a.D, a.D, L.y, L.dim);
   if (L.status != kSuccess)
@@ -154,11 +156,14 @@ __device__ void finish_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
 
 // One attempted step of one instance (accept or reject), in the order of the
 // reference algorithm: stages, error norm, controller, dense output, commit.
-template <typename R, class M, class F>
-__device__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
+// REC: write the attempt record; KEEP: keep the interpolant for solver_eval.
+// The controller is branch-free (selects); only the rare paths (dense output,
+// the step limit) branch.
+template <typename R, class M, class F, bool REC, bool KEEP>
+__device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
                         const F& f) {
   constexpr int N = F::N;
-  if (L.n_att >= a.ctrl.max_steps) {
+  if (__builtin_expect(L.n_att >= a.ctrl.max_steps, 0)) {
     L.status = kMaxSteps;
     return;
   }
@@ -187,46 +192,38 @@ __device__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
   R acc = R(0);
 #pragma unroll
   for (int q = 0; q < N; ++q) {
-    if (q < L.dim) {
-      R eq = R(0);
+    R eq = R(0);
 #pragma unroll
-      for (int j = 0; j < 7; ++j)
-        if (M::E[j] != 0.0) eq += R(M::E[j]) * L.k[j][q];
-      eq *= hs;
-      const R sc = L.atol + L.rtol * rmax(rabs(L.y[q]), rabs(Y[q]));
-      const R r = eq / sc;
-      acc += r * r;
-    }
+    for (int j = 0; j < 7; ++j)
+      if (M::E[j] != 0.0) eq += R(M::E[j]) * L.k[j][q];
+    eq *= hs;
+    const R sc = L.atol + L.rtol * rmax(rabs(L.y[q]), rabs(Y[q]));
+    const R r = ctl_div(eq, sc);
+    if (N == 2 || q < L.dim) acc += r * r;
   }
-  const R err = rsqrt_(acc / R(L.dim));
+  const R err = ctl_sqrt(N == 2 ? acc * R(0.5) : ctl_div(acc, R(L.dim)));
   const bool accept = err < R(1);
-  // Attempt record: every attempted step size, negated when rejected.
-  if (a.h_rec != nullptr && L.n_att <= a.rec_cap)
+  if (REC && L.n_att <= a.rec_cap)
     a.h_rec[(long)L.inst * a.rec_cap + L.n_att - 1] =
         accept ? double(hs) : -double(hs);
 
-  R fac;
+  // Controller: on acceptance clamp(safety err^-beta1 err_prev^beta2), capped
+  // at 1 after a rejection; on rejection max(fac_min, safety err^-1/5); a
+  // non-finite err gives fac_min (err = 0 reaches fac_max through the clamp).
+  // L.err_prev holds err_prev^beta2, formed when that step was accepted.
   const Ctrl& c = a.ctrl;
-  if (!__builtin_isfinite(err)) {
-    fac = R(c.fac_min);
-  } else if (accept) {
-    if (err == R(0)) {
-      fac = R(c.fac_max);
-    } else {
-      fac = R(c.safety) * rpow(err, R(-c.beta1));
-      if (c.beta2 != 0.0) fac *= rpow(L.err_prev, R(c.beta2));
-      fac = rmin(R(c.fac_max), rmax(R(c.fac_min), fac));
-    }
-    if (L.prev_rej) fac = rmin(R(1), fac);
-  } else {
-    fac = rmax(R(c.fac_min), R(c.safety) * rpow(err, R(-0.2)));
-  }
+  const R pw = ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
+  R fac = R(c.safety) * pw;
+  fac = accept ? fac * L.err_prev : fac;
+  fac = rmax(R(c.fac_min), accept ? rmin(R(c.fac_max), fac) : fac);
+  fac = (accept && L.prev_rej) ? rmin(R(1), fac) : fac;
+  fac = __builtin_isfinite(err) ? fac : R(c.fac_min);
 
   if (accept) {
     const double tnew = last ? L.te : L.t + double(hs);
     // Dense output at this instance's own evaluation times in (t, t_new]
     // (Horner in theta, then the stage combination).
-    while (L.next_te <= tnew) {
+    while (__builtin_expect(L.next_te <= tnew, 0)) {
       const R th = R((L.next_te - L.t) / double(hs));
       R w[7];
 #pragma unroll
@@ -250,7 +247,7 @@ __device__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
                       ? a.t_eval[(long)L.inst * a.E + L.cursor]
                       : INFINITY;
     }
-    if (a.keep_dense) {
+    if (KEEP) {
       const int i = L.inst;
       a.dk.t_prev[i] = L.t;
       a.dk.h_last[i] = hs;
@@ -270,18 +267,20 @@ __device__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
       }
     }
     L.t = tnew;
+    if (last) L.status = kSuccess;
+    L.err_prev = c.beta2 != 0.0
+                     ? ctl_pow(rmax(err, R(1e-4)), R(c.beta2))
+                     : R(1);
+    L.n_acc += 1;
+  }
+  L.n_rej += accept ? 0 : 1;
+  L.prev_rej = accept ? 0 : 1;
+  if (accept) {
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       L.y[q] = Y[q];
       L.k[0][q] = L.k[6][q];  // FSAL
     }
-    L.err_prev = rmax(err, R(1e-4));
-    L.n_acc += 1;
-    L.prev_rej = 0;
-    if (last) L.status = kSuccess;
-  } else {
-    L.n_rej += 1;
-    L.prev_rej = 1;
   }
   L.h = hs * fac;
   if (L.status == kRunning && !(double(L.h) > 16.0 * DBL_EPSILON * fabs(L.t)))
@@ -289,14 +288,14 @@ __device__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
 }
 
 template <typename R>
-__device__ int fetch(const AnalyticArgs<R>& a, int kind) {
+__device__ __forceinline__ int fetch(const AnalyticArgs<R>& a, int kind) {
   const int p = atomicAdd(&a.counts[2 + kind], 1);
   const int n = __atomic_load_n(&a.counts[kind], __ATOMIC_RELAXED);
   if (p >= n) return -1;
   return kind == kKindVdp ? a.list[p] : a.list[a.B - 1 - p];
 }
 
-template <typename R, class M, class F>
+template <typename R, class M, class F, bool REC, bool KEEP>
 __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
                                                     int kind) {
   Lane<R, F::N> L;
@@ -308,7 +307,7 @@ __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
       f.load(a, inst, L.dim);
       int used = 0;
       while (L.status == kRunning && used < a.budget) {
-        attempt<R, M, F>(a, L, f);
+        attempt<R, M, F, REC, KEEP>(a, L, f);
         ++used;
       }
       if (L.status == kRunning)
@@ -323,7 +322,7 @@ __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
 // ---- initialisation ----------------------------------------------------------
 
 template <typename R>
-__device__ bool instance_ok(const AnalyticArgs<R>& a, int i) {
+__device__ __forceinline__ bool instance_ok(const AnalyticArgs<R>& a, int i) {
   const int kind = a.kind[i], dim = a.dim[i];
   if (kind == kKindVdp) {
     if (dim != 2 || a.D < 2 || a.mu == nullptr) return false;
@@ -352,7 +351,7 @@ __device__ bool instance_ok(const AnalyticArgs<R>& a, int i) {
 
 // Hairer's starting step (Solving ODEs I, II.4) from f0 = f(t0, y0).
 template <typename R, class F>
-__device__ R start_step(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
+__device__ __forceinline__ R start_step(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
                         const F& f) {
   constexpr int N = F::N;
   const double span = L.te - L.t;
@@ -391,7 +390,7 @@ __device__ R start_step(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
 }
 
 template <typename R, class F>
-__device__ void init_one(const AnalyticArgs<R>& a, int i) {
+__device__ __forceinline__ void init_one(const AnalyticArgs<R>& a, int i) {
   constexpr int N = F::N;
   Lane<R, N> L;
   F f;
@@ -498,6 +497,23 @@ hipError_t launch_analytic_init(const AnalyticArgs<R>& a, int, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename R, class M, class F>
+void launch_solve_flags(const AnalyticArgs<R>& a, int kind, dim3 g, dim3 b,
+                        hipStream_t s) {
+  const bool rec = a.h_rec != nullptr, keep = a.keep_dense != 0;
+  if (rec && keep)
+    hipLaunchKernelGGL((solve_kernel<R, M, F, true, true>), g, b, 0, s, a, kind);
+  else if (rec)
+    hipLaunchKernelGGL((solve_kernel<R, M, F, true, false>), g, b, 0, s, a,
+                       kind);
+  else if (keep)
+    hipLaunchKernelGGL((solve_kernel<R, M, F, false, true>), g, b, 0, s, a,
+                       kind);
+  else
+    hipLaunchKernelGGL((solve_kernel<R, M, F, false, false>), g, b, 0, s, a,
+                       kind);
+}
+
 template <typename R>
 hipError_t launch_analytic_solve(const AnalyticArgs<R>& a, int method,
                                  int kind, int lanes, int block,
@@ -506,20 +522,17 @@ hipError_t launch_analytic_solve(const AnalyticArgs<R>& a, int method,
   if (lanes <= 0) lanes = a.B;
   const int grid = (lanes + block - 1) / block;
   if (grid == 0) return hipSuccess;
+  const dim3 g(grid), b(block);
   if (kind == kKindVdp) {
     if (method == 1)
-      hipLaunchKernelGGL((solve_kernel<R, Tsit5, VdpField<R>>), dim3(grid),
-                         dim3(block), 0, s, a, kind);
+      launch_solve_flags<R, Tsit5, VdpField<R>>(a, kind, g, b, s);
     else
-      hipLaunchKernelGGL((solve_kernel<R, Dopri5, VdpField<R>>), dim3(grid),
-                         dim3(block), 0, s, a, kind);
+      launch_solve_flags<R, Dopri5, VdpField<R>>(a, kind, g, b, s);
   } else {
     if (method == 1)
-      hipLaunchKernelGGL((solve_kernel<R, Tsit5, LinearField<R>>), dim3(grid),
-                         dim3(block), 0, s, a, kind);
+      launch_solve_flags<R, Tsit5, LinearField<R>>(a, kind, g, b, s);
     else
-      hipLaunchKernelGGL((solve_kernel<R, Dopri5, LinearField<R>>),
-                         dim3(grid), dim3(block), 0, s, a, kind);
+      launch_solve_flags<R, Dopri5, LinearField<R>>(a, kind, g, b, s);
   }
   return hipGetLastError();
 }

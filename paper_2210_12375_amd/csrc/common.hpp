@@ -30,7 +30,7 @@ template <typename R>
 struct State {
   double* t;         // current time
   R* h;              // next step size to try
-  R* err_prev;       // error norm of the last accepted step (PI term)
+  R* err_prev;       // err_prev^beta2 of the last accepted step (PI term)
   int32_t* n_att;    // attempted steps
   int32_t* n_acc;    // accepted steps
   int32_t* n_rej;    // rejected steps
@@ -71,6 +71,25 @@ __device__ __forceinline__ double rpow(double x, double y) { return pow(x, y); }
 __device__ __forceinline__ float rpow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double rsqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float rsqrt_(float x) { return sqrtf(x); }
+
+// Controller and norm arithmetic.  FP64 (the validation mode) stays correctly
+// rounded; the reduced-precision modes use the hardware reciprocal, square
+// root, log2 and exp2 (about 1 ulp), which is far below the float rounding
+// noise of an embedded error estimate.
+__device__ __forceinline__ double ctl_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float ctl_div(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+__device__ __forceinline__ double ctl_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float ctl_sqrt(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+__device__ __forceinline__ double ctl_pow(double x, double y) {
+  return pow(x, y);
+}
+__device__ __forceinline__ float ctl_pow(float x, float y) {
+  return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+}
 
 template <typename R>
 __device__ __forceinline__ R quiet_nan();

