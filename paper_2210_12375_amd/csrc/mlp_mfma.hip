@@ -1,0 +1,391 @@
+// Neural right-hand sides on BF16 MFMA (gfx950 v_mfma_f32_16x16x32_bf16).
+//
+// One workgroup (4 wavefronts) evaluates the field for a tile of instances.
+// Its prologue forms each instance's stage input Y = y + h sum_j a_sj k_j in
+// FP32 (the stage combination of the Runge-Kutta step), splits it into
+// bf16 hi + lo (two MFMAs per product, so activation rounding does not
+// masquerade as local error), and stages it in LDS.  Weights are BF16,
+// packed once per solve into 16x32 B-fragments (1 KiB contiguous per
+// fragment, read straight from L2 by each wavefront).  Accumulation is FP32;
+// biases, the time input (a rank-1 term t * W1[t, :]) and tanh are applied in
+// the epilogue, whose output is split again into LDS for the next layer.
+//
+// For the CNF field the tangent rows (the Jacobian-vector product with the
+// Rademacher probe) are stacked under the primal rows of the same 16-row
+// MFMA tile (8 + 8): the tangent epilogue takes tanh' from the partner lane
+// (lane ^ 32 holds the same column of the primal row 8 above).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "mlp_mfma.hpp"
+
+namespace bode {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u)  // inf / nan stay inf / nan
+    return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) {
+  return __uint_as_float(uint32_t(h) << 16);
+}
+
+struct Dims {
+  int K1, nk1, nn1, nk2, nn2, nk3, nn3;
+  size_t off2, off3;  // packed offsets (elements) of layers 2 and 3
+};
+
+__host__ __device__ inline Dims dims(int din, int H) {
+  Dims d;
+  d.K1 = (din + 31) / 32 * 32;
+  d.nk1 = d.K1 / 32;
+  d.nn1 = H / 16;
+  d.nk2 = H / 32;
+  d.nn2 = H / 16;
+  d.nk3 = H / 32;
+  d.nn3 = din / 16;
+  d.off2 = (size_t)d.nk1 * d.nn1 * 512;
+  d.off3 = d.off2 + (size_t)d.nk2 * d.nn2 * 512;
+  return d;
+}
+
+// Fragment f = kb * nn + nb, lane l, element i holds W[kb*32 + (l/16)*8 + i]
+// [nb*16 + l%16] (zero beyond K rows).
+__global__ void pack_kernel(uint16_t* dst, const float* W, int K, int ldw,
+                            int nk, int nn) {
+  const long total = (long)nk * nn * 512;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = e & 7, l = (e >> 3) & 63;
+    const long f = e >> 9;
+    const int kb = int(f / nn), nb = int(f % nn);
+    const int k = kb * 32 + (l >> 4) * 8 + i, n = nb * 16 + (l & 15);
+    dst[e] = k < K ? f2bf(W[(long)k * ldw + n]) : uint16_t(0);
+  }
+}
+
+__global__ void fvec_kernel(float* f, const float* W1, const float* b1,
+                            const float* b2, const float* b3, int din, int H) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < 3 * H + din;
+       j += gridDim.x * blockDim.x) {
+    float v;
+    if (j < H)
+      v = b1[j];
+    else if (j < 2 * H)
+      v = W1[(long)din * H + (j - H)];  // time row of W1
+    else if (j < 3 * H)
+      v = b2[j - 2 * H];
+    else
+      v = b3[j - 3 * H];
+    f[j] = v;
+  }
+}
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__device__ __forceinline__ bf16x8 gld8(const uint16_t* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// C[MT][NTW] += A(LDS hi + lo, MT 16-row tiles, K = 32 nk) x B(packed,
+// columns of n-tiles nb0 + t * nstep).
+template <int MT, int NTW>
+__device__ __forceinline__ void gemm(f32x4 (&acc)[MT][NTW], const uint16_t* Ah,
+                                     const uint16_t* Al, int lda,
+                                     const uint16_t* Bp, int nk, int nn,
+                                     int nb0, int nstep, int ntiles,
+                                     int lane) {
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  for (int kb = 0; kb < nk; ++kb) {
+    bf16x8 ah[MT], al[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int off = (mt * 16 + r) * lda + kb * 32 + kq;
+      ah[mt] = lds8(Ah + off);
+      al[mt] = lds8(Al + off);
+    }
+    bf16x8 bfrag[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      const int nb = nb0 + t * nstep;
+      if (t < ntiles)
+        bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb) * 64 + lane) * 8);
+    }
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      if (t < ntiles) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
+          acc[mt][t] = mfma(al[mt], bfrag[t], acc[mt][t]);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void put_split(uint16_t* Ah, uint16_t* Al, int off,
+                                          float v) {
+  const uint16_t h = f2bf(v);
+  Ah[off] = h;
+  Al[off] = f2bf(v - bf2f(h));
+}
+
+// MT 16-row tiles per workgroup (MLP: 16 MT instances; CNF: MT = 1 holds
+// 8 instances and their 8 tangent rows); NTW = H / 64 column tiles per
+// wavefront in the hidden layers.
+template <int MT, int NTW, bool CNF>
+__global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
+  constexpr int RT = 16 * MT;
+  constexpr int PR = CNF ? 8 : RT;  // instances per workgroup
+  constexpr int H = NTW * 64;
+  constexpr int SA = H + 8;  // LDS row stride of activations (bank spread)
+  const int din = a.din, D = a.D, B = a.B;
+  const Dims dm = dims(din, H);
+  const int SX = dm.K1 + 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint16_t* Xh = reinterpret_cast<uint16_t*>(smem_raw);
+  uint16_t* Xl = Xh + RT * SX;
+  uint16_t* Ah = Xl + RT * SX;
+  uint16_t* Al = Ah + RT * SA;
+  float* tcol = reinterpret_cast<float*>(Al + RT * SA);  // [PR]
+  float* red = tcol + PR;                                 // [PR][nn3]
+  __shared__ int any_running;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.x * PR;
+  if (tid == 0) any_running = 0;
+  __syncthreads();
+  if (tid < PR && r0 + tid < B && a.status[r0 + tid] == kRunning)
+    any_running = 1;
+  __syncthreads();
+  if (!any_running) return;
+
+  // prologue: stage input (FP32) -> split bf16 in LDS; tangent rows = probe
+  for (int idx = tid; idx < PR * D; idx += blockDim.x) {
+    const int r = idx / D, c = idx % D, row = r0 + r;
+    float Yv = 0.f;
+    if (row < B) {
+      float acc = 0.f;
+      for (int j = 0; j < a.n; ++j)
+        acc += a.coef[j] * a.K[((long)a.kidx[j] * B + row) * D + c];
+      Yv = a.y[(long)row * D + c] + a.hs[row] * acc;
+      if (a.write_y7) a.Y7[(long)row * D + c] = Yv;
+    }
+    if (c < din) put_split(Xh, Xl, r * SX + c, Yv);
+  }
+  for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
+    const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
+    Xh[r * SX + c] = 0;
+    Xl[r * SX + c] = 0;
+  }
+  if (CNF) {
+    for (int idx = tid; idx < PR * din; idx += blockDim.x) {
+      const int r = idx / din, c = idx % din, row = r0 + r;
+      const float e = row < B ? a.eps[(long)row * D + c] : 0.f;
+      put_split(Xh, Xl, (PR + r) * SX + c, e);
+    }
+  }
+  for (int r = tid; r < PR; r += blockDim.x) {
+    const int row = r0 + r;
+    tcol[r] = row < B ? float(a.t[row] + a.c * double(a.hs[row])) : 0.f;
+  }
+  __syncthreads();
+
+  const float* b1 = a.w.fvec;
+  const float* w1t = b1 + H;
+  const float* b2 = b1 + 2 * H;
+  const float* b3 = b1 + 3 * H;
+  const int rq = (lane >> 4) * 4, col = lane & 15;
+
+  // hidden layers: wave w owns column tiles w * NTW .. w * NTW + NTW - 1
+  for (int layer = 0; layer < 2; ++layer) {
+    f32x4 acc[MT][NTW];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (layer == 0)
+      gemm<MT, NTW>(acc, Xh, Xl, SX, a.w.packed, dm.nk1, dm.nn1, wave * NTW, 1,
+                    NTW, lane);
+    else
+      gemm<MT, NTW>(acc, Ah, Al, SA, a.w.packed + dm.off2, dm.nk2, dm.nn2,
+                    wave * NTW, 1, NTW, lane);
+    __syncthreads();  // every wave has read its layer input
+    const float* bias = layer == 0 ? b1 : b2;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = mt * 16 + rq + i;
+          float v = acc[mt][t][i];
+          const bool primal = !CNF || row < PR;
+          if (primal) {
+            v += bias[n];
+            if (layer == 0) v += tcol[row] * w1t[n];
+          }
+          float act = primal ? tanhf(v) : 0.f;
+          if (CNF) {
+            const float ap = __shfl_xor(act, 32, 64);  // primal of row - 8
+            if (!primal) act = (1.f - ap * ap) * v;
+          }
+          put_split(Ah, Al, row * SA + n, act);
+        }
+      }
+    __syncthreads();
+  }
+
+  // output layer: column tiles nb = wave, wave + 4, ...
+  {
+    const int ntiles = (dm.nn3 - wave + 3) / 4;
+    f32x4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (ntiles > 0)
+      gemm<MT, 4>(acc, Ah, Al, SA, a.w.packed + dm.off3, dm.nk3, dm.nn3, wave,
+                  4, ntiles, lane);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= ntiles) continue;
+        const int nb = wave + 4 * t;
+        const int n = nb * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = mt * 16 + rq + i;
+          const float v = acc[mt][t][i];
+          if (!CNF || r < PR) {
+            const int row = r0 + r;
+            if (row < B) a.out[(long)row * D + n] = v + b3[n];
+          } else {
+            // tangent row: eps_n * (dg/dz eps)_n, summed over the 16 columns
+            const int pr = r - PR, row = r0 + pr;
+            float q = row < B ? a.eps[(long)row * D + n] * v : 0.f;
+            q += __shfl_xor(q, 1, 64);
+            q += __shfl_xor(q, 2, 64);
+            q += __shfl_xor(q, 4, 64);
+            q += __shfl_xor(q, 8, 64);
+            if (col == 0) red[pr * dm.nn3 + nb] = q;
+          }
+        }
+      }
+    if (CNF) {
+      __syncthreads();
+      for (int pr = tid; pr < PR; pr += blockDim.x) {
+        const int row = r0 + pr;
+        float q = 0.f;
+        for (int nb = 0; nb < dm.nn3; ++nb) q += red[pr * dm.nn3 + nb];
+        if (row < B) a.out[(long)row * D + din] = -q;
+      }
+    }
+  }
+}
+
+template <int MT, int NTW, bool CNF>
+size_t mfma_smem(int din) {
+  constexpr int RT = 16 * MT, PR = CNF ? 8 : RT, H = NTW * 64;
+  const Dims dm = dims(din, H);
+  return sizeof(uint16_t) * 2 * ((size_t)RT * (dm.K1 + 8) + RT * (H + 8)) +
+         sizeof(float) * (PR + PR * dm.nn3);
+}
+
+template <int MT, int NTW, bool CNF>
+hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
+  constexpr int PR = CNF ? 8 : 16 * MT;
+  const size_t sm = mfma_smem<MT, NTW, CNF>(a.din);
+  if (sm > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((field_mfma_kernel<MT, NTW, CNF>),
+                     dim3((a.B + PR - 1) / PR), dim3(256), sm, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t mfma_packed_elems(int din, int H) {
+  const Dims d = dims(din, H);
+  return d.off3 + (size_t)d.nk3 * d.nn3 * 512;
+}
+
+size_t mfma_fvec_elems(int din, int H) { return 3 * (size_t)H + din; }
+
+std::string mfma_supported(int din, int H) {
+  if (din < 16 || din % 16 != 0 || din > 256)
+    return "BF16 fields need a state width that is a multiple of 16, <= 256";
+  if (H != 128 && H != 256 && H != 512)
+    return "BF16 fields are built for hidden widths 128, 256 and 512";
+  return "";
+}
+
+hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
+                             const float* W1, const float* b1, const float* W2,
+                             const float* b2, const float* W3, const float* b3,
+                             hipStream_t s) {
+  const Dims d = dims(din, H);
+  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, w.packed, W1,
+                     din, H, d.nk1, d.nn1);
+  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
+                     w.packed + d.off2, W2, H, H, d.nk2, d.nn2);
+  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
+                     w.packed + d.off3, W3, H, din, d.nk3, d.nn3);
+  hipLaunchKernelGGL(fvec_kernel, dim3(8), dim3(256), 0, s, w.fvec, W1, b1, b2,
+                     b3, din, H);
+  return hipGetLastError();
+}
+
+MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
+                   const float* y, const float* K, float* Y7, const float* hs,
+                   const double* t, const float* eps, const MfmaWeights& w) {
+  MfmaArgs a{};
+  a.B = B;
+  a.D = D;
+  a.din = din;
+  a.H = H;
+  a.cnf = cnf;
+  a.status = status;
+  a.y = y;
+  a.K = K;
+  a.Y7 = Y7;
+  a.hs = hs;
+  a.t = t;
+  a.eps = eps;
+  a.w = w;
+  return a;
+}
+
+hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s) {
+  if (a.cnf) {
+    if (a.H == 512) return launch_t<1, 8, true>(a, s);
+    if (a.H == 256) return launch_t<1, 4, true>(a, s);
+    return launch_t<1, 2, true>(a, s);
+  }
+  const bool big = row_tile == 32 || (row_tile == 0 && a.B >= 32 * 512);
+  if (a.H == 512) return big ? launch_t<2, 8, false>(a, s)
+                             : launch_t<1, 8, false>(a, s);
+  if (a.H == 256) return big ? launch_t<2, 4, false>(a, s)
+                             : launch_t<1, 4, false>(a, s);
+  return big ? launch_t<2, 2, false>(a, s) : launch_t<1, 2, false>(a, s);
+}
+
+}  // namespace bode

@@ -1,0 +1,53 @@
+// BF16 MFMA evaluation of the neural fields (MLP and CNF), gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace bode {
+
+// Packed weights: every layer as 16x32 MFMA B-fragments (64 lanes x 8 bf16,
+// 1 KiB contiguous per fragment), plus FP32 vectors b1, w1t (the time row
+// of W1), b2, b3.
+struct MfmaWeights {
+  uint16_t* packed = nullptr;
+  float* fvec = nullptr;
+};
+
+size_t mfma_packed_elems(int din, int H);
+size_t mfma_fvec_elems(int din, int H);
+std::string mfma_supported(int din, int H);
+
+hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
+                             const float* W1, const float* b1, const float* W2,
+                             const float* b2, const float* W3, const float* b3,
+                             hipStream_t s);
+
+struct MfmaArgs {
+  int B, D, din, H, cnf;
+  const int32_t* status;
+  const float* y;
+  const float* K;  // [7, B, D]
+  float* Y7;
+  const float* hs;
+  const double* t;
+  const float* eps;
+  MfmaWeights w;
+  int n;
+  int kidx[6];
+  float coef[6];
+  double c;
+  int write_y7;
+  float* out;
+};
+
+MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
+                   const float* y, const float* K, float* Y7, const float* hs,
+                   const double* t, const float* eps, const MfmaWeights& w);
+
+// row_tile 0 picks the default for the shape.
+hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s);
+
+}  // namespace bode

@@ -1,0 +1,135 @@
+"""GPU parity of the neural right-hand sides (MLP and CNF fields) through the
+C ABI.
+
+FP64 mode (FMA field kernel): identical counts and statuses and outputs
+within 1e-9 of the free-running FP64 oracle, plus the decision-by-decision
+replay check.  FP32 mode: the oracle replays the GPU's attempt record on the
+float-rounded inputs, 1e-4.  BF16 mode (MFMA, split-BF16 activations, BF16
+weights): the same replay, 1e-2 (the benchmark spec's bound for a BF16 right-hand
+side); step counts reported against FP64.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import (TOL_BF16, TOL_FP32, as_float_inputs,
+                         assert_fp64_parity, oracle_replay,
+                         per_instance_absdiff, replay_check, run_gpu)
+from paper_2210_12375_amd import binding as bd
+from paper_2210_12375_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+def replay_rel(p, g, method):
+    q = as_float_inputs(p)
+    r = oracle_replay(q, g, method)
+    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
+                                       r["y_final"])
+    return diff / np.maximum(scale, 1e-300)
+
+
+@pytest.mark.parametrize("method", ["dopri5", "tsit5"])
+def test_mlp_fp64_parity(method):
+    flush(f"mlp fp64 {method}")
+    p = W.neural_ode(B=192)
+    g, _ = run_gpu(p, method=method, rhs=bd.RHS_MLP, record_cap=256)
+    r = oracle.solve(p, method=method)
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
+    replay_check(p, g, method)
+    flush(f"  steps p50 {np.median(g['n_accepted'])}")
+
+
+def test_mlp_fp64_eval_times_and_edges():
+    """Eight fixed evaluation times (the fwd+bwd workload's), a user h0, an
+    instance with t_end = t0, an invalid one, B not a multiple of the tile."""
+    flush("mlp fp64 eval times, edges")
+    p = W.neural_ode_fit(B=77)
+    p["t_end"][5] = 0.0
+    p["t_eval"][5] = 0.0
+    p["rtol"][9] = -1.0
+    g, _ = run_gpu(p, method="dopri5", rhs=bd.RHS_MLP, record_cap=256)
+    r = oracle.solve(p, method="dopri5")
+    np.testing.assert_array_equal(g["status"], r["status"])
+    assert g["status"][5] == bd.SUCCESS and g["status"][9] == bd.INVALID
+    ok = r["status"] != bd.INVALID
+    assert_fp64_parity({k: v[ok] for k, v in g.items()},
+                       {k: v[ok] for k, v in r.items()})
+    q = W.subset(p, np.flatnonzero(ok))
+    q["h0"] = np.full(q["y0"].shape[0], 0.05)
+    g, _ = run_gpu(q, method="tsit5", rhs=bd.RHS_MLP)
+    r = oracle.solve(q, method="tsit5")
+    assert_fp64_parity(g, r)
+    np.testing.assert_array_equal(g["n_feval"], 1 + 6 * g["n_attempted"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32),
+                                           ("bf16", TOL_BF16)])
+def test_mlp_reduced_precision_replay(precision, tol):
+    flush(f"mlp {precision} replay")
+    p = W.neural_ode(B=512)
+    g, _ = run_gpu(p, method="dopri5", precision=precision, rhs=bd.RHS_MLP,
+                   record_cap=256)
+    assert np.all(g["status"] == bd.SUCCESS)
+    rel = replay_rel(p, g, "dopri5")
+    assert rel.max() <= tol, (rel.max(), np.argmax(rel))
+    r = oracle.solve(p, method="dopri5")
+    infl = g["n_accepted"].mean() / r["n_accepted"].mean()
+    flush(f"  max rel {rel.max():.2e}, steps {g['n_accepted'].mean():.2f} vs "
+          f"FP64 {r['n_accepted'].mean():.2f} (x{infl:.2f})")
+    assert infl < 2.0
+
+
+def test_mlp_bf16_full_size_sampled():
+    """The 4096-instance neural-ODE workload in BF16; 64 sampled instances
+    replayed by the oracle."""
+    flush("mlp bf16 full 4096")
+    p = W.neural_ode()
+    g, _ = run_gpu(p, method="dopri5", precision="bf16", rhs=bd.RHS_MLP,
+                   record_cap=256)
+    assert np.all(g["status"] == bd.SUCCESS)
+    idx = np.random.default_rng(5).choice(p["y0"].shape[0], 64, replace=False)
+    rel = replay_rel(W.subset(p, idx), {k: v[idx] for k, v in g.items()},
+                     "dopri5")
+    assert rel.max() <= TOL_BF16, rel.max()
+    np.testing.assert_array_equal(g["n_attempted"],
+                                  g["n_accepted"] + g["n_rejected"])
+
+
+def test_cnf_fp64_parity():
+    flush("cnf fp64")
+    p = W.cnf_density(B=48)
+    g, _ = run_gpu(p, method="dopri5", rhs=bd.RHS_CNF, record_cap=256)
+    r = oracle.solve(p, method="dopri5")
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
+    replay_check(p, g, "dopri5")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32),
+                                           ("bf16", TOL_BF16)])
+def test_cnf_reduced_precision_replay(precision, tol):
+    flush(f"cnf {precision} replay")
+    p = W.cnf_density(B=256)
+    g, _ = run_gpu(p, method="tsit5", precision=precision, rhs=bd.RHS_CNF,
+                   record_cap=256)
+    assert np.all(g["status"] == bd.SUCCESS)
+    rel = replay_rel(p, g, "tsit5")
+    assert rel.max() <= tol, (rel.max(), np.argmax(rel))
+
+
+def test_cnf_bf16_full_size_sampled():
+    flush("cnf bf16 full 8192")
+    p = W.cnf_density()
+    g, _ = run_gpu(p, method="dopri5", precision="bf16", rhs=bd.RHS_CNF,
+                   record_cap=256)
+    assert np.all(g["status"] == bd.SUCCESS)
+    idx = np.random.default_rng(6).choice(p["y0"].shape[0], 32, replace=False)
+    rel = replay_rel(W.subset(p, idx), {k: v[idx] for k, v in g.items()},
+                     "dopri5")
+    assert rel.max() <= TOL_BF16, rel.max()
