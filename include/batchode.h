@@ -104,6 +104,9 @@ typedef struct {
   int32_t mlp_hidden; /* MLP / CNF hidden width (both hidden layers)         */
   int32_t tune_block; /* launch tuning (0 = library / autotuned default)     */
   int32_t tune_lanes;
+  int32_t ckpt_every; /* neural fields: keep y_n every ckpt_every accepted
+                         steps for solver_backward (0: no checkpoints); the
+                         backward recomputes the states in between          */
 } bode_config;
 
 /* Problem description: device pointers (NULL where not used). */

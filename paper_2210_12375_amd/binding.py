@@ -41,7 +41,8 @@ class Config(C.Structure):
                 ("safety", C.c_double), ("fac_min", C.c_double),
                 ("fac_max", C.c_double), ("record_cap", C.c_int32),
                 ("keep_dense", C.c_int32), ("mlp_hidden", C.c_int32),
-                ("tune_block", C.c_int32), ("tune_lanes", C.c_int32)]
+                ("tune_block", C.c_int32), ("tune_lanes", C.c_int32),
+                ("ckpt_every", C.c_int32)]
 
 
 _PROBLEM_FIELDS = ["y0", "t0", "t_end", "rtol", "atol", "t_eval", "h0", "kind",
@@ -112,7 +113,7 @@ def make_config(B, D, E=0, method="dopri5", precision="fp64",
                 rhs=RHS_ANALYTIC, max_steps=100000, beta1=PI_CONTROLLER["beta1"],
                 beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2,
                 fac_max=10.0, record_cap=0, keep_dense=0, mlp_hidden=0,
-                tune_block=0, tune_lanes=0):
+                tune_block=0, tune_lanes=0, ckpt_every=0):
     c = Config()
     c.method = METHODS[method] if isinstance(method, str) else method
     c.precision = (PRECISIONS[precision] if isinstance(precision, str)
@@ -122,6 +123,7 @@ def make_config(B, D, E=0, method="dopri5", precision="fp64",
     c.fac_min, c.fac_max = fac_min, fac_max
     c.record_cap, c.keep_dense, c.mlp_hidden = record_cap, keep_dense, mlp_hidden
     c.tune_block, c.tune_lanes = tune_block, tune_lanes
+    c.ckpt_every = ckpt_every
     return c
 
 

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
       for (int j = 0; j < a.n; ++j)
         acc += a.coef[j] * a.K[((long)a.kidx[j] * B + row) * D + c];
       Yv = a.y[(long)row * D + c] + a.hs[row] * acc;
-      if (a.write_y7) a.Y7[(long)row * D + c] = Yv;
+      if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
     }
     if (c < din) put_split(Xh, Xl, r * SX + c, Yv);
   }

@@ -56,6 +56,8 @@ struct Mod {
   DenseKeep<R> dk;
   int32_t keep;
   Ctrl ctrl;
+  R* ckpt;          // [B, ck_cap, D] y_n for n = 0, k, 2k, ... (or nullptr)
+  int32_t ck_every, ck_cap;
 };
 
 // Stage input Y = y + hs * sum_j coef_j K[kidx_j]; field time t + c hs.
@@ -64,7 +66,7 @@ struct StageSpec {
   int kidx[6];
   double coef[6];
   double c;
-  int write_y7;
+  void* yout;  // if not null, the stage input Y is written here ([B, D])
 };
 
 template <class M>
@@ -78,8 +80,37 @@ StageSpec stage_spec(int s) {  // s = 1..6 (stage s+1)
       ++sp.n;
     }
   sp.c = M::C[s];
-  sp.write_y7 = (s == 6);
+  sp.yout = nullptr;
   return sp;
+}
+
+// Buffers of the discrete-adjoint backward (workspace views).
+template <typename R>
+struct Back {
+  double* hacc;    // [B, cap] accepted step sizes, in order
+  double* tn;      // [B, cap + 1] step start times
+  int32_t* nacc;   // [B] accepted steps in the record
+  int32_t* owner;  // [B, E] step answering each evaluation time (-1: t0)
+  int32_t* act;    // [B] status view: running iff step n exists
+  R* bh;           // [B] h_n of the step being processed
+  double* bt;      // [B] t_n
+  R* lam;          // [B, D] cotangent of y_n+1 / y_n
+  R* lamn;         // [B, D] cotangent of y_n being accumulated
+  R* kap;          // [7, B, D] stage cotangents
+  R* Ys;           // [7, B, D] stage inputs of step n
+  R* Ks;           // [7, B, D] stage values
+  R* yseg;         // [k + 1, B, D] states of the current segment
+  R* slots;        // [G, P] per-workgroup parameter-gradient partials
+  int32_t* flags;  // [0]: max accepted steps, [1]: record overflow
+  int32_t cap, k, G;
+  long P;
+};
+
+constexpr int kSlots = 64;
+
+inline long n_params(int din, int H) {
+  const long n0 = din + 1;
+  return n0 * H + H + (long)H * H + H + (long)H * din + din;
 }
 
 // ---- field kernel (FMA path: FP64 validation mode and FP32 mode) -------------
@@ -127,7 +158,7 @@ __global__ __launch_bounds__(256) void field_fma_kernel(Mod<R> m, StageSpec sp,
       for (int j = 0; j < sp.n; ++j)
         acc += R(sp.coef[j]) * m.K[((long)sp.kidx[j] * B + row) * D + c];
       Yv = m.st.y[(long)row * D + c] + m.hs[row] * acc;
-      if (sp.write_y7) m.Y7[(long)row * D + c] = Yv;
+      if (sp.yout) static_cast<R*>(sp.yout)[(long)row * D + c] = Yv;
     }
     if (c < din) {
       X[r * n0 + c] = Yv;
@@ -321,8 +352,10 @@ __global__ void mod_init_rows(Mod<R> m) {
       m.y_eval[(long)row * E * D + e] = quiet_nan<R>();
     return;
   }
-  for (int c = lane; c < D; c += 64)
+  for (int c = lane; c < D; c += 64) {
     st.y[(long)row * D + c] = m.y0[(long)row * D + c];
+    if (m.ckpt) m.ckpt[(long)row * m.ck_cap * D + c] = m.y0[(long)row * D + c];
+  }
   int cursor = 0;
   while (cursor < E && m.t_eval[(long)row * E + cursor] <= t0) {
     for (int c = lane; c < D; c += 64)
@@ -494,9 +527,15 @@ __global__ __launch_bounds__(256) void commit_kernel(Mod<R> m) {
         }
       }
     }
+    const int nacc = m.st.n_acc[row] + 1;
+    const bool ck = m.ckpt != nullptr && nacc % m.ck_every == 0 &&
+                    nacc / m.ck_every < m.ck_cap;
     for (int cc = lane; cc < D; cc += 64) {
-      m.st.y[(long)row * D + cc] = m.Y7[(long)row * D + cc];
+      const R yn = m.Y7[(long)row * D + cc];
+      m.st.y[(long)row * D + cc] = yn;
       m.K[(long)row * D + cc] = m.K[((long)6 * B + row) * D + cc];  // FSAL
+      if (ck)
+        m.ckpt[((long)row * m.ck_cap + nacc / m.ck_every) * D + cc] = yn;
     }
     t = tnew;
     if (last) status = kSuccess;
@@ -552,6 +591,8 @@ struct ModImpl {
   bode_problem p{};
   Mod<double> md{};
   Mod<float> mf{};
+  Back<double> bd{};
+  Back<float> bf{};
   MfmaWeights mw{};  // BF16 packed weights (BF16 precision)
   bool is64 = false;
   int32_t* host_running = nullptr;  // pinned
@@ -572,7 +613,8 @@ struct Lay {
 };
 
 template <typename R>
-size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw) {
+size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
+               Back<R>* bkout) {
   Lay L{static_cast<char*>(base)};
   const size_t B = c.B, D = c.D;
   State<R> st{};
@@ -603,6 +645,36 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw) {
     dk.q = L.take<R>(4 * B * D);
   }
   const int din = c.rhs == BODE_RHS_CNF ? c.D - 1 : c.D;
+  R* ckpt = nullptr;
+  int ck_cap = 0;
+  if (c.ckpt_every > 0) {
+    ck_cap = c.record_cap / c.ckpt_every + 2;
+    ckpt = L.take<R>(B * (size_t)ck_cap * D);
+  }
+  Back<R> bk{};
+  if (c.record_cap > 0) {
+    const size_t cap = c.record_cap;
+    const int k = c.ckpt_every > 0 ? c.ckpt_every : c.record_cap;
+    bk.cap = c.record_cap;
+    bk.k = k;
+    bk.P = n_params(din, c.mlp_hidden);
+    bk.G = kSlots;
+    bk.hacc = L.take<double>(B * cap);
+    bk.tn = L.take<double>(B * (cap + 1));
+    bk.nacc = L.take<int32_t>(B);
+    bk.owner = L.take<int32_t>(B * (size_t)(c.E > 0 ? c.E : 1));
+    bk.act = L.take<int32_t>(B);
+    bk.bh = L.take<R>(B);
+    bk.bt = L.take<double>(B);
+    bk.lam = L.take<R>(B * D);
+    bk.lamn = L.take<R>(B * D);
+    bk.kap = L.take<R>(7 * B * D);
+    bk.Ys = L.take<R>(7 * B * D);
+    bk.Ks = L.take<R>(7 * B * D);
+    bk.yseg = L.take<R>((size_t)(k + 1) * B * D);
+    bk.slots = L.take<R>((size_t)bk.G * bk.P);
+    bk.flags = L.take<int32_t>(64);
+  }
   MfmaWeights w{};
   if (c.precision == BODE_BF16) {
     const size_t n = mfma_packed_elems(din, c.mlp_hidden);
@@ -621,7 +693,11 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw) {
     m->rec_cap = c.record_cap;
     m->dk = dk;
     m->keep = c.keep_dense;
+    m->ckpt = ckpt;
+    m->ck_every = c.ckpt_every;
+    m->ck_cap = ck_cap;
   }
+  if (bkout) *bkout = bk;
   if (mw) *mw = w;
   return L.off + 256;
 }
@@ -676,7 +752,8 @@ hipError_t field<float>(ModImpl& im, const Mod<float>& m, const StageSpec& sp,
       a.coef[j] = float(sp.coef[j]);
     }
     a.c = sp.c;
-    a.write_y7 = sp.write_y7;
+    a.write_y7 = sp.yout != nullptr;
+    a.Y7 = static_cast<float*>(sp.yout);
     a.out = out;
     return launch_field_mfma(a, get_row_tile(im.cfg), s);
   }
@@ -691,8 +768,11 @@ dim3 row_grid(int B) {
 template <typename R, class M>
 hipError_t round_launch(ModImpl& im, Mod<R>& m, hipStream_t s) {
   hipError_t e = launch_fill_i32(m.n_running, 1, 0, s);
-  for (int st = 1; st < 7 && e == hipSuccess; ++st)
-    e = field<R>(im, m, stage_spec<M>(st), m.K + (size_t)st * m.B * m.D, s);
+  for (int st = 1; st < 7 && e == hipSuccess; ++st) {
+    StageSpec sp = stage_spec<M>(st);
+    if (st == 6) sp.yout = m.Y7;
+    e = field<R>(im, m, sp, m.K + (size_t)st * m.B * m.D, s);
+  }
   if (e != hipSuccess) return e;
   if (m.keep)
     hipLaunchKernelGGL((commit_kernel<R, M, true>), row_grid<R>(m.B),
@@ -767,10 +847,12 @@ std::string modular_supported(const bode_config& c) {
 size_t modular_layout(const bode_config& c, void* base, ModularPlan* mp) {
   if (c.precision == BODE_FP64) {
     Mod<double> m{};
-    const size_t n = lay_mod<double>(c, base, mp ? &m : nullptr, nullptr);
+    Back<double> bk{};
+    const size_t n = lay_mod<double>(c, base, mp ? &m : nullptr, nullptr, &bk);
     if (mp) {
       ModImpl* im = new ModImpl();
       im->md = m;
+      im->bd = bk;
       im->is64 = true;
       mp->impl = im;
     }
@@ -778,10 +860,12 @@ size_t modular_layout(const bode_config& c, void* base, ModularPlan* mp) {
   }
   Mod<float> m{};
   MfmaWeights w{};
-  const size_t n = lay_mod<float>(c, base, mp ? &m : nullptr, &w);
+  Back<float> bk{};
+  const size_t n = lay_mod<float>(c, base, mp ? &m : nullptr, &w, &bk);
   if (mp) {
     ModImpl* im = new ModImpl();
     im->mf = m;
+    im->bf = bk;
     im->mw = w;
     mp->impl = im;
   }
@@ -795,7 +879,7 @@ hipError_t modular_init(ModularPlan& mp, const bode_config& c,
   im->cfg = c;
   im->p = p;
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&im->host_running),
-                               sizeof(int32_t), hipHostMallocDefault);
+                               2 * sizeof(int32_t), hipHostMallocDefault);
   if (e != hipSuccess) return e;
   auto publish = [&](auto& m) {
     mp.t = m.st.t;
@@ -828,6 +912,499 @@ hipError_t modular_init(ModularPlan& mp, const bode_config& c,
   return init_launch<float>(*im, im->mf, s);
 }
 
+// ---- discrete adjoint ----------------------------------------------------------
+//
+// Paper section 4.2 trains its graph model by backpropagating through the
+// solver.  This is the discrete adjoint of the accepted steps with their sizes
+// and decisions frozen (rejected attempts and the controller carry no
+// gradient).  For step n (sizes h_n, start t_n, state y_n):
+//   Y_1 = y_n, k_s = f(t_n + c_s h, Y_s), Y_s = y_n + h sum_{j<s} a_sj k_j,
+//   y_n+1 = Y_7, dense output y(theta) = y_n + h sum_j w_j(theta) k_j.
+// Walking the stages backwards: kappa_j collects h w_j(theta_e) g_e from the
+// step's evaluation times; stage 7 only feeds the interpolant, so
+// Lambda = lambda + J_7^T kappa_7 and kappa_j += h a_7j Lambda; then for
+// s = 6..1: mu_s = J_s^T kappa_s, kappa_j += h a_sj mu_s (j < s); finally
+// lambda_n = Lambda + sum_s mu_s + sum_e g_e.  Parameter gradients collect
+// (df/dtheta)^T kappa_s at every stage.  y_n comes from a checkpoint every k
+// accepted steps and is recomputed in between (the field kernel of the
+// forward replays the recorded steps).
+
+struct VjpSpec {
+  int s;  // stage 1..7
+  int n;
+  int kidx[6];
+  double coef[6];
+  double c;
+};
+
+template <typename R>
+__global__ void adj_prep(Mod<R> m, Back<R> b) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= m.B) return;
+  const int status = m.st.status[row];
+  const int natt = m.st.n_att[row];
+  int N = 0;
+  if (status != kInvalid) {
+    if (natt > b.cap) {
+      atomicOr(&b.flags[1], 1);
+    } else {
+      for (int q = 0; q < natt; ++q) {
+        const double h = m.h_rec[(long)row * m.rec_cap + q];
+        if (h > 0.0) b.hacc[(long)row * b.cap + N++] = h;
+      }
+    }
+  }
+  double* tn = b.tn + (long)row * (b.cap + 1);
+  tn[0] = m.t0[row];
+  for (int q = 0; q < N; ++q)
+    tn[q + 1] = (q == N - 1 && status == kSuccess) ? m.t_end[row]
+                                                    : tn[q] + b.hacc[(long)row * b.cap + q];
+  int cursor = 0;
+  const double* te = m.t_eval + (long)row * m.E;
+  int32_t* own = b.owner + (long)row * (m.E > 0 ? m.E : 1);
+  while (cursor < m.E && te[cursor] <= tn[0]) own[cursor++] = -1;
+  for (int q = 0; q < N; ++q)
+    while (cursor < m.E && te[cursor] <= tn[q + 1]) own[cursor++] = q;
+  while (cursor < m.E) own[cursor++] = -2;  // never reached
+  b.nacc[row] = N;
+  atomicMax(&b.flags[0], N);
+}
+
+// Step n of every instance that has one: status view, h_n, t_n; optionally
+// y_n -> Y_1 (the differentiated step keeps its stage inputs).
+template <typename R>
+__global__ void adj_setup(Mod<R> m, Back<R> b, int n, const R* yn, R* y1) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= m.B) return;
+  const bool on = n < b.nacc[row];
+  if (lane == 0) {
+    b.act[row] = on ? kRunning : kSuccess;
+    b.bh[row] = on ? R(b.hacc[(long)row * b.cap + n]) : R(0);
+    b.bt[row] = on ? b.tn[(long)row * (b.cap + 1) + n] : 0.0;
+  }
+  if (y1 != nullptr && on)
+    for (int c = lane; c < m.D; c += 64)
+      y1[(long)row * m.D + c] = yn[(long)row * m.D + c];
+}
+
+// Segment start: y_{seg k} from the checkpoints (or y0).
+template <typename R>
+__global__ void adj_load_ckpt(Mod<R> m, Back<R> b, int seg, R* dst) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long total = (long)m.B * m.D;
+  if (i >= total) return;
+  const long row = i / m.D, c = i % m.D;
+  dst[i] = m.ckpt != nullptr ? m.ckpt[(row * m.ck_cap + seg) * m.D + c]
+                             : m.y0[i];
+}
+
+// Cotangents injected by the dense outputs of step n.
+template <typename R, class M>
+__global__ void adj_dense(Mod<R> m, Back<R> b, int n, const R* g_eval) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= m.B) return;
+  const int D = m.D, B = m.B;
+  for (int c = lane; c < D; c += 64) {
+    b.lamn[(long)row * D + c] = R(0);
+    for (int j = 0; j < 7; ++j) b.kap[((long)j * B + row) * D + c] = R(0);
+  }
+  if (!(n < b.nacc[row]) || m.E == 0) return;
+  const double h = b.hacc[(long)row * b.cap + n];
+  const double t = b.tn[(long)row * (b.cap + 1) + n];
+  const int32_t* own = b.owner + (long)row * m.E;
+  for (int e = 0; e < m.E; ++e) {
+    if (own[e] != n) continue;
+    const R th = R((m.t_eval[(long)row * m.E + e] - t) / h);
+    R w[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+      w[j] = th * (R(M::P[j][0]) +
+                   th * (R(M::P[j][1]) + th * (R(M::P[j][2]) + th * R(M::P[j][3]))));
+    for (int c = lane; c < D; c += 64) {
+      const R g = g_eval[((long)row * m.E + e) * D + c];
+      for (int j = 0; j < 7; ++j)
+        b.kap[((long)j * B + row) * D + c] += R(h) * w[j] * g;
+      b.lamn[(long)row * D + c] += g;
+    }
+  }
+}
+
+// mu_s = J_f(Y_s)^T kappa_s for a tile of instances (the field's layers are
+// recomputed in LDS), the parameter gradient added into this workgroup's
+// slot, and the row updates of kappa, lambda.
+template <typename R, int ROWS>
+__global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
+                                                  VjpSpec sp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* sm = reinterpret_cast<R*>(smem_raw);
+  const int B = m.B, D = m.D, H = m.H, din = m.d_in, n0 = din + 1;
+  const int cnf = m.cnf;
+  R* X = sm;                  // [ROWS][n0]
+  R* Kp = X + ROWS * n0;      // [ROWS][D]  kappa_s
+  R* A1 = Kp + ROWS * D;      // [ROWS][H]
+  R* A2 = A1 + ROWS * H;
+  R* G1 = A2 + ROWS * H;      // pbar1
+  R* G2 = G1 + ROWS * H;      // pbar2
+  R* MU = G2 + ROWS * H;      // [ROWS][din]
+  R* dX = MU + ROWS * din;    // CNF: probe, tangents and their cotangents
+  R* DP1 = dX + ROWS * n0;
+  R* DA1 = DP1 + ROWS * H;
+  R* DP2 = DA1 + ROWS * H;
+  R* DA2 = DP2 + ROWS * H;
+  R* DG1 = DA2 + ROWS * H;    // dpbar1
+  R* DG2 = DG1 + ROWS * H;    // dpbar2
+  __shared__ int any;
+  R* slot = b.slots + (long)blockIdx.x * b.P;
+  const int s = sp.s;
+  const R* Yin = b.Ys + (long)(s - 1) * B * D;
+  const R* Kin = b.kap + (long)(s - 1) * B * D;
+  const int ntiles = (B + ROWS - 1) / ROWS;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int r0 = tile * ROWS;
+    __syncthreads();
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    if (threadIdx.x < ROWS && r0 + threadIdx.x < B &&
+        b.act[r0 + threadIdx.x] == kRunning)
+      any = 1;
+    __syncthreads();
+    if (!any) continue;
+    for (int idx = threadIdx.x; idx < ROWS * D; idx += blockDim.x) {
+      const int r = idx / D, c = idx % D, row = r0 + r;
+      const bool on = row < B && b.act[row] == kRunning;
+      Kp[idx] = on ? Kin[(long)row * D + c] : R(0);
+      if (c < din) {
+        X[r * n0 + c] = on ? Yin[(long)row * D + c] : R(0);
+        if (cnf) dX[r * n0 + c] = on ? m.eps[(long)row * D + c] : R(0);
+      }
+    }
+    for (int r = threadIdx.x; r < ROWS; r += blockDim.x) {
+      const int row = r0 + r;
+      const bool on = row < B && b.act[row] == kRunning;
+      X[r * n0 + din] = on ? R(b.bt[row] + sp.c * double(b.bh[row])) : R(0);
+      if (cnf) dX[r * n0 + din] = R(0);
+    }
+    __syncthreads();
+    // forward: a1, a2 (and the tangents for the CNF)
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+      for (int r = 0; r < ROWS; ++r) {
+        R acc = m.b1[j], tac = R(0);
+        for (int i = 0; i < n0; ++i) {
+          acc += X[r * n0 + i] * m.W1[(long)i * H + j];
+          if (cnf && i < din) tac += dX[r * n0 + i] * m.W1[(long)i * H + j];
+        }
+        const R a = tanh(acc);
+        A1[r * H + j] = a;
+        if (cnf) {
+          DP1[r * H + j] = tac;
+          DA1[r * H + j] = (R(1) - a * a) * tac;
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+      for (int r = 0; r < ROWS; ++r) {
+        R acc = m.b2[j], tac = R(0);
+        for (int i = 0; i < H; ++i) {
+          acc += A1[r * H + i] * m.W2[(long)i * H + j];
+          if (cnf) tac += DA1[r * H + i] * m.W2[(long)i * H + j];
+        }
+        const R a = tanh(acc);
+        A2[r * H + j] = a;
+        if (cnf) {
+          DP2[r * H + j] = tac;
+          DA2[r * H + j] = (R(1) - a * a) * tac;
+        }
+      }
+    }
+    __syncthreads();
+    // output layer backwards: gbar = kappa_z, dgbar = -kappa_l eps
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+      for (int r = 0; r < ROWS; ++r) {
+        R s1 = R(0), s2 = R(0);
+        for (int j = 0; j < din; ++j) {
+          const R w = m.W3[(long)i * din + j];
+          s1 += w * Kp[r * D + j];
+          if (cnf) s2 += w * (-Kp[r * D + din] * dX[r * n0 + j]);
+        }
+        const R a = A2[r * H + i], g = R(1) - a * a;
+        if (cnf) {
+          const R dpb = g * s2;
+          DG2[r * H + i] = dpb;
+          s1 += R(-2) * a * DP2[r * H + i] * s2;
+        }
+        G2[r * H + i] = g * s1;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+      for (int r = 0; r < ROWS; ++r) {
+        R s1 = R(0), s2 = R(0);
+        for (int j = 0; j < H; ++j) {
+          const R w = m.W2[(long)i * H + j];
+          s1 += w * G2[r * H + j];
+          if (cnf) s2 += w * DG2[r * H + j];
+        }
+        const R a = A1[r * H + i], g = R(1) - a * a;
+        if (cnf) {
+          DG1[r * H + i] = g * s2;
+          s1 += R(-2) * a * DP1[r * H + i] * s2;
+        }
+        G1[r * H + i] = g * s1;
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ROWS * din; idx += blockDim.x) {
+      const int r = idx / din, c = idx % din;
+      R acc = R(0);
+      for (int j = 0; j < H; ++j) acc += m.W1[(long)c * H + j] * G1[r * H + j];
+      MU[idx] = acc;
+    }
+    // parameter gradients into this workgroup's slot (fixed order: no atomics)
+    const long o_b1 = (long)n0 * H, o_W2 = o_b1 + H, o_b2 = o_W2 + (long)H * H;
+    const long o_W3 = o_b2 + H, o_b3 = o_W3 + (long)H * din;
+    for (long p = threadIdx.x; p < b.P; p += blockDim.x) {
+      R v = R(0);
+      if (p < o_b1) {
+        const int i = int(p / H), j = int(p % H);
+        for (int r = 0; r < ROWS; ++r) {
+          v += X[r * n0 + i] * G1[r * H + j];
+          if (cnf && i < din) v += dX[r * n0 + i] * DG1[r * H + j];
+        }
+      } else if (p < o_W2) {
+        const int j = int(p - o_b1);
+        for (int r = 0; r < ROWS; ++r) v += G1[r * H + j];
+      } else if (p < o_b2) {
+        const long q = p - o_W2;
+        const int i = int(q / H), j = int(q % H);
+        for (int r = 0; r < ROWS; ++r) {
+          v += A1[r * H + i] * G2[r * H + j];
+          if (cnf) v += DA1[r * H + i] * DG2[r * H + j];
+        }
+      } else if (p < o_W3) {
+        const int j = int(p - o_b2);
+        for (int r = 0; r < ROWS; ++r) v += G2[r * H + j];
+      } else if (p < o_b3) {
+        const long q = p - o_W3;
+        const int i = int(q / din), j = int(q % din);
+        for (int r = 0; r < ROWS; ++r) {
+          v += A2[r * H + i] * Kp[r * D + j];
+          if (cnf) v += DA2[r * H + i] * (-Kp[r * D + din] * dX[r * n0 + j]);
+        }
+      } else {
+        const int j = int(p - o_b3);
+        for (int r = 0; r < ROWS; ++r) v += Kp[r * D + j];
+      }
+      slot[p] += v;
+    }
+    __syncthreads();
+    // row updates: kappa_j += h a_sj mu (Lambda at stage 7), lambda sums
+    for (int idx = threadIdx.x; idx < ROWS * D; idx += blockDim.x) {
+      const int r = idx / D, c = idx % D, row = r0 + r;
+      if (row >= B || b.act[row] != kRunning) continue;
+      const R h = b.bh[row];
+      R mu = c < din ? MU[r * din + c] : R(0);
+      const long o = (long)row * D + c;
+      if (s == 7) {
+        mu = b.lam[o] + mu;  // Lambda
+        b.lam[o] = mu;
+      }
+      b.lamn[o] += mu;
+      for (int j = 0; j < sp.n; ++j)
+        b.kap[((long)sp.kidx[j] * B + row) * D + c] += h * R(sp.coef[j]) * mu;
+      if (s == 1) b.lam[o] = b.lamn[o];
+    }
+  }
+}
+
+template <typename R>
+size_t vjp_smem(int rows, int n0, int D, int H, int din, int cnf) {
+  size_t per = (size_t)n0 + D + 4 * (size_t)H + din;
+  if (cnf) per += (size_t)n0 + 6 * (size_t)H;
+  return sizeof(R) * rows * per;
+}
+
+template <typename R>
+hipError_t launch_vjp(const Mod<R>& m, const Back<R>& b, const VjpSpec& sp,
+                      hipStream_t s) {
+  const int n0 = m.d_in + 1;
+  int rows = 8;
+  while (rows > 1 && vjp_smem<R>(rows, n0, m.D, m.H, m.d_in, m.cnf) > 65536)
+    rows /= 2;
+  const size_t sm = vjp_smem<R>(rows, n0, m.D, m.H, m.d_in, m.cnf);
+  if (sm > 65536) return hipErrorInvalidValue;
+  const int ntiles = (m.B + rows - 1) / rows;
+  const dim3 g(ntiles < b.G ? ntiles : b.G), blk(256);
+  switch (rows) {
+    case 8:
+      hipLaunchKernelGGL((vjp_kernel<R, 8>), g, blk, sm, s, m, b, sp);
+      break;
+    case 4:
+      hipLaunchKernelGGL((vjp_kernel<R, 4>), g, blk, sm, s, m, b, sp);
+      break;
+    case 2:
+      hipLaunchKernelGGL((vjp_kernel<R, 2>), g, blk, sm, s, m, b, sp);
+      break;
+    default:
+      hipLaunchKernelGGL((vjp_kernel<R, 1>), g, blk, sm, s, m, b, sp);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void fill_r(R* p, long n, R v) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename R>
+__global__ void copy_r(R* dst, const R* src, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// dtheta = sum of the slots in slot order (deterministic).
+template <typename R>
+__global__ void reduce_slots(const R* slots, int G, long P, R* out) {
+  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  R acc = R(0);
+  for (int g = 0; g < G; ++g) acc += slots[(long)g * P + p];
+  out[p] = acc;
+}
+
+// dy0 = lambda_0 + cotangents of evaluation times at t0; NaN for invalid.
+template <typename R>
+__global__ void adj_finish(Mod<R> m, Back<R> b, const R* g_eval, R* dy0) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)m.B * m.D) return;
+  const long row = i / m.D, c = i % m.D;
+  if (m.st.status[row] == kInvalid) {
+    dy0[i] = quiet_nan<R>();
+    return;
+  }
+  R v = b.lam[i];
+  for (int e = 0; e < m.E; ++e)
+    if (b.owner[row * m.E + e] == -1) v += g_eval[(row * m.E + e) * m.D + c];
+  dy0[i] = v;
+}
+
+namespace {
+
+inline dim3 lin_grid(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+template <typename R, class M>
+hipError_t stages(ModImpl& im, Mod<R> v, Back<R>& b, R* y7dst, bool keep_y,
+                  hipStream_t s) {
+  // v.st.y = y_n, v.hs = h_n, v.st.t = t_n, v.st.status = act, v.K = Ks
+  StageSpec sp0{};
+  hipError_t e = field<R>(im, v, sp0, b.Ks, s);
+  for (int st = 1; st < 7 && e == hipSuccess; ++st) {
+    StageSpec sp = stage_spec<M>(st);
+    if (keep_y)
+      sp.yout = b.Ys + (size_t)st * v.B * v.D;
+    else if (st == 6)
+      sp.yout = y7dst;
+    e = field<R>(im, v, sp, b.Ks + (size_t)st * v.B * v.D, s);
+  }
+  return e;
+}
+
+template <typename R, class M>
+hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
+                      const R* g_final, R* dy0, R* dtheta, hipStream_t s) {
+  const long BD = (long)m.B * m.D;
+  const dim3 rows_g((m.B + 3) / 4), blk(256);
+  hipLaunchKernelGGL(fill_r<R>, lin_grid(b.G * b.P), blk, 0, s, b.slots,
+                     (long)b.G * b.P, R(0));
+  hipLaunchKernelGGL(copy_r<R>, lin_grid(BD), blk, 0, s, b.lam, g_final, BD);
+  hipError_t e = launch_fill_i32(b.flags, 2, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_prep<R>, dim3((m.B + 255) / 256), blk, 0, s, m, b);
+  e = hipMemcpyAsync(im.host_running, b.flags, sizeof(int32_t) * 2,
+                     hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  const int nmax = im.host_running[0];
+  if (im.host_running[1] != 0) return hipErrorInvalidValue;  // record overflow
+  Mod<R> v = m;  // view of the forward's field inputs onto the backward buffers
+  v.hs = b.bh;
+  v.st.t = b.bt;
+  v.st.status = b.act;
+  v.K = b.Ks;
+  const int k = b.k;
+  for (int n = nmax - 1; n >= 0; --n) {
+    const int seg = n / k, base = seg * k;
+    if (n == nmax - 1 || n == base + k - 1) {
+      // entering a segment from above: states y_base .. y_n by recomputation
+      hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b, seg,
+                         b.yseg);
+      for (int mm = base; mm < n; ++mm) {
+        R* ym = b.yseg + (size_t)(mm - base) * BD;
+        hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
+                           (const R*)nullptr, (R*)nullptr);
+        v.st.y = ym;
+        e = stages<R, M>(im, v, b, ym + BD, false, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+    R* yn = b.yseg + (size_t)(n - base) * BD;
+    hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n, (const R*)yn,
+                       b.Ys);
+    v.st.y = yn;
+    e = stages<R, M>(im, v, b, nullptr, true, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval);
+    for (int st = 7; st >= 1; --st) {
+      VjpSpec sp{};
+      sp.s = st;
+      sp.c = M::C[st - 1];
+      // kappa_j receives h a_{s j} mu_s for the stages j < s
+      const StageSpec ss = stage_spec<M>(st - 1 > 0 ? st - 1 : 0);
+      sp.n = st - 1 > 0 ? ss.n : 0;
+      for (int j = 0; j < sp.n; ++j) {
+        sp.kidx[j] = ss.kidx[j];
+        sp.coef[j] = ss.coef[j];
+      }
+      e = launch_vjp<R>(m, b, sp, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(adj_finish<R>, lin_grid(BD), blk, 0, s, m, b, g_eval,
+                     dy0);
+  hipLaunchKernelGGL(reduce_slots<R>, lin_grid(b.P), blk, 0, s, b.slots, b.G,
+                     b.P, dtheta);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t backward_m(ModImpl& im, Mod<R>& m, Back<R>& b, const void* ge,
+                      const void* gf, void* dy0, void* dth, hipStream_t s) {
+  const R* g_eval = static_cast<const R*>(ge);
+  if (im.cfg.method == BODE_TSIT5)
+    return backward_t<R, Tsit5>(im, m, b, g_eval, static_cast<const R*>(gf),
+                                static_cast<R*>(dy0), static_cast<R*>(dth), s);
+  return backward_t<R, Dopri5>(im, m, b, g_eval, static_cast<const R*>(gf),
+                               static_cast<R*>(dy0), static_cast<R*>(dth), s);
+}
+
+}  // namespace
+
+hipError_t modular_backward(ModularPlan& mp, const void* g_y_eval,
+                            const void* g_y_final, void* dy0, void* dtheta,
+                            hipStream_t s) {
+  ModImpl* im = static_cast<ModImpl*>(mp.impl);
+  if (!im || im->cfg.record_cap < 1) return hipErrorInvalidValue;
+  if (im->is64)
+    return backward_m<double>(*im, im->md, im->bd, g_y_eval, g_y_final, dy0,
+                              dtheta, s);
+  return backward_m<float>(*im, im->mf, im->bf, g_y_eval, g_y_final, dy0,
+                           dtheta, s);
+}
+
 hipError_t modular_run(ModularPlan& mp, int budget, hipStream_t s) {
   ModImpl* im = static_cast<ModImpl*>(mp.impl);
   if (!im) return hipErrorInvalidValue;
@@ -847,10 +1424,6 @@ hipError_t modular_eval(ModularPlan& mp, const double* t_query, void* y_out,
                                   t_query, static_cast<float*>(y_out), qstatus,
                                   s);
 }
-
-hipError_t modular_backward(ModularPlan& mp, const void* g_y_eval,
-                            const void* g_y_final, void* dy0, void* dtheta,
-                            hipStream_t s);
 
 void modular_release(ModularPlan& mp) {
   ModImpl* im = static_cast<ModImpl*>(mp.impl);

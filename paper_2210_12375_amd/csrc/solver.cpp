@@ -124,6 +124,9 @@ std::string check_config(const bode_config* c) {
     return "controller needs safety > 0, 0 < fac_min <= 1 <= fac_max, "
            "beta1, beta2 >= 0";
   if (c->record_cap < 0) return "record_cap must be >= 0";
+  if (c->ckpt_every < 0) return "ckpt_every must be >= 0";
+  if (c->ckpt_every > 0 && c->record_cap < 1)
+    return "checkpoints need record_cap > 0";
   if (c->rhs != BODE_RHS_ANALYTIC && c->mlp_hidden < 1)
     return "mlp_hidden must be >= 1 for neural right-hand sides";
   if ((long)c->B * (long)std::max(c->D, 1) * std::max(c->E, 1) > (1L << 40))
