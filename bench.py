@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-neural", action="store_true",
+                    help="skip the neural-field workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
                          "the reference kernel for HBM byte counters")
@@ -183,6 +185,71 @@ def cpu_baseline(p, method, seconds):
                       f"{dt * 1e3:.1f} ms per pass"}
 
 
+def neural_suite(bd, W, rl, steps, warmup):
+    """The neural-field workloads: forward solves (accepted instance-steps/s)
+    and forward + discrete-adjoint backward passes (fwd+bwd/s)."""
+    import torch
+    out = {}
+
+    def run(p, rhs, precision, backward, nsteps):
+        dp = bd.device_problem(p, precision)
+        opts = dict(method="dopri5", precision=precision, rhs=rhs)
+        if backward:
+            opts.update(record_cap=256, ckpt_every=2)
+        P = sum(np.asarray(p["mlp"][k]).size
+                for k in ("W1", "b1", "W2", "b2", "W3", "b3"))
+        sd = torch.float64 if precision == "fp64" else torch.float32
+        g_final = torch.ones(p["y0"].shape, dtype=sd, device="cuda")
+        E = p["t_eval"].shape[1]
+        g_eval = (torch.ones((p["y0"].shape[0], E, p["y0"].shape[1]),
+                             dtype=sd, device="cuda") if E else None)
+        times = []
+        st = None
+        for k in range(warmup + nsteps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = bd.Solver(dp, **opts).solve()
+            if backward:
+                s.backward(g_eval, g_final, P)
+            torch.cuda.synchronize()
+            if k >= warmup:
+                times.append(time.perf_counter() - t0)
+            if k == warmup + nsteps - 1:
+                st = {kk: v.cpu().numpy() for kk, v in s.stats().items()}
+            s.close()
+        ms = float(np.median(times)) * 1e3
+        acc = int(st["n_accepted"].sum())
+        rounds = int(st["n_attempted"].max())
+        d = p["y0"].shape[1] - (1 if rhs == bd.RHS_CNF else 0)
+        H = p["mlp"]["W1"].shape[1]
+        evals = (2 + 6 * rounds) * p["y0"].shape[0]  # rows the kernels touch
+        fl = evals * rl.mlp_flops_per_row(d, H) * (2 if rhs == bd.RHS_CNF else 1)
+        r = dict(ms=ms, accepted=acc, steps_mean=float(st["n_accepted"].mean()),
+                 rounds=rounds, ok=bool(np.all(st["status"] == 1)),
+                 model_tflops=fl / (ms * 1e-3) / 1e12)
+        if backward:
+            r["fwd_bwd_per_s"] = 1e3 / ms
+        else:
+            r["instance_steps_per_s"] = acc / (ms * 1e-3)
+        return r
+
+    p3 = W.neural_ode()
+    out["neural_fwd_4096_bf16"] = run(p3, bd.RHS_MLP, "bf16", False, steps)
+    out["neural_fwd_4096_fp64"] = run(p3, bd.RHS_MLP, "fp64", False,
+                                      max(1, steps // 2))
+    p4 = W.neural_ode_fit()
+    out["neural_fwdbwd_1024_bf16"] = run(p4, bd.RHS_MLP, "bf16", True, steps)
+    out["neural_fwdbwd_1024_fp32"] = run(p4, bd.RHS_MLP, "fp32", True, steps)
+    p5 = W.cnf_density()
+    out["cnf_fwdbwd_8192_bf16"] = run(p5, bd.RHS_CNF, "bf16", True,
+                                      max(1, steps // 2))
+    for k, v in out.items():
+        print(f"# {k}: {v['ms']:.2f} ms, {v['steps_mean']:.2f} steps, "
+              f"{v['model_tflops']:.1f} model TFLOP/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -289,6 +356,9 @@ def main():
                                     "steps_max", "steps_hist", "ok")}
                      for (m, pr), r in results.items()},
     }
+    if not a.no_neural:
+        line["neural"] = neural_suite(bd, W, rl, max(2, a.steps // 4),
+                                      min(a.warmup, 2))
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.method, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -2,9 +2,10 @@
 //
 // One workgroup (4 wavefronts) evaluates the field for a tile of instances.
 // Its prologue forms each instance's stage input Y = y + h sum_j a_sj k_j in
-// FP32 (the stage combination of the Runge-Kutta step), splits it into
-// bf16 hi + lo (two MFMAs per product, so activation rounding does not
-// masquerade as local error), and stages it in LDS.  Weights are BF16,
+// FP32 (the stage combination of the Runge-Kutta step), splits it into three
+// bf16 terms hi + mid + lo (24 significant bits, FP32's precision: three MFMAs
+// per product, so activation rounding does not masquerade as local error at
+// tolerances near 1e-5), and stages it in LDS.  Weights are BF16,
 // packed once per solve into 16x32 B-fragments (1 KiB contiguous per
 // fragment, read straight from L2 by each wavefront).  Accumulation is FP32;
 // biases, the time input (a rank-1 term t * W1[t, :]) and tanh are applied in
@@ -103,22 +104,23 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// C[MT][NTW] += A(LDS hi + lo, MT 16-row tiles, K = 32 nk) x B(packed,
-// columns of n-tiles nb0 + t * nstep).
+// C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
+// B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit at
+// Ah, Ah + plane, Ah + 2 plane.
 template <int MT, int NTW>
 __device__ __forceinline__ void gemm(f32x4 (&acc)[MT][NTW], const uint16_t* Ah,
-                                     const uint16_t* Al, int lda,
-                                     const uint16_t* Bp, int nk, int nn,
-                                     int nb0, int nstep, int ntiles,
-                                     int lane) {
+                                     int plane, int lda, const uint16_t* Bp,
+                                     int nk, int nn, int nb0, int nstep,
+                                     int ntiles, int lane) {
   const int r = lane & 15, kq = (lane >> 4) * 8;
   for (int kb = 0; kb < nk; ++kb) {
-    bf16x8 ah[MT], al[MT];
+    bf16x8 ah[MT], am[MT], al[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int off = (mt * 16 + r) * lda + kb * 32 + kq;
       ah[mt] = lds8(Ah + off);
-      al[mt] = lds8(Al + off);
+      am[mt] = lds8(Ah + plane + off);
+      al[mt] = lds8(Ah + 2 * plane + off);
     }
     bf16x8 bfrag[NTW];
 #pragma unroll
@@ -132,19 +134,24 @@ __device__ __forceinline__ void gemm(f32x4 (&acc)[MT][NTW], const uint16_t* Ah,
       if (t < ntiles) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
           acc[mt][t] = mfma(al[mt], bfrag[t], acc[mt][t]);
+          acc[mt][t] = mfma(am[mt], bfrag[t], acc[mt][t]);
+          acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
         }
       }
     }
   }
 }
 
-__device__ __forceinline__ void put_split(uint16_t* Ah, uint16_t* Al, int off,
+// v = hi + mid + lo in bf16 (terms at Ah, Ah + plane, Ah + 2 plane).
+__device__ __forceinline__ void put_split(uint16_t* Ah, int plane, int off,
                                           float v) {
   const uint16_t h = f2bf(v);
+  const float r1 = v - bf2f(h);
+  const uint16_t m = f2bf(r1);
   Ah[off] = h;
-  Al[off] = f2bf(v - bf2f(h));
+  Ah[plane + off] = m;
+  Ah[2 * plane + off] = f2bf(r1 - bf2f(m));
 }
 
 // MT 16-row tiles per workgroup (MLP: 16 MT instances; CNF: MT = 1 holds
@@ -160,11 +167,10 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
   const Dims dm = dims(din, H);
   const int SX = dm.K1 + 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int PX = RT * SX, PA = RT * SA;  // split-term planes
   uint16_t* Xh = reinterpret_cast<uint16_t*>(smem_raw);
-  uint16_t* Xl = Xh + RT * SX;
-  uint16_t* Ah = Xl + RT * SX;
-  uint16_t* Al = Ah + RT * SA;
-  float* tcol = reinterpret_cast<float*>(Al + RT * SA);  // [PR]
+  uint16_t* Ah = Xh + 3 * PX;
+  float* tcol = reinterpret_cast<float*>(Ah + 3 * PA);  // [PR]
   float* red = tcol + PR;                                 // [PR][nn3]
   __shared__ int any_running;
 
@@ -188,18 +194,17 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
       Yv = a.y[(long)row * D + c] + a.hs[row] * acc;
       if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
     }
-    if (c < din) put_split(Xh, Xl, r * SX + c, Yv);
+    if (c < din) put_split(Xh, PX, r * SX + c, Yv);
   }
   for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
     const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
-    Xh[r * SX + c] = 0;
-    Xl[r * SX + c] = 0;
+    put_split(Xh, PX, r * SX + c, 0.f);
   }
   if (CNF) {
     for (int idx = tid; idx < PR * din; idx += blockDim.x) {
       const int r = idx / din, c = idx % din, row = r0 + r;
       const float e = row < B ? a.eps[(long)row * D + c] : 0.f;
-      put_split(Xh, Xl, (PR + r) * SX + c, e);
+      put_split(Xh, PX, (PR + r) * SX + c, e);
     }
   }
   for (int r = tid; r < PR; r += blockDim.x) {
@@ -222,10 +227,10 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
 #pragma unroll
       for (int t = 0; t < NTW; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 0)
-      gemm<MT, NTW>(acc, Xh, Xl, SX, a.w.packed, dm.nk1, dm.nn1, wave * NTW, 1,
+      gemm<MT, NTW>(acc, Xh, PX, SX, a.w.packed, dm.nk1, dm.nn1, wave * NTW, 1,
                     NTW, lane);
     else
-      gemm<MT, NTW>(acc, Ah, Al, SA, a.w.packed + dm.off2, dm.nk2, dm.nn2,
+      gemm<MT, NTW>(acc, Ah, PA, SA, a.w.packed + dm.off2, dm.nk2, dm.nn2,
                     wave * NTW, 1, NTW, lane);
     __syncthreads();  // every wave has read its layer input
     const float* bias = layer == 0 ? b1 : b2;
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
             const float ap = __shfl_xor(act, 32, 64);  // primal of row - 8
             if (!primal) act = (1.f - ap * ap) * v;
           }
-          put_split(Ah, Al, row * SA + n, act);
+          put_split(Ah, PA, row * SA + n, act);
         }
       }
     __syncthreads();
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
-      gemm<MT, 4>(acc, Ah, Al, SA, a.w.packed + dm.off3, dm.nk3, dm.nn3, wave,
+      gemm<MT, 4>(acc, Ah, PA, SA, a.w.packed + dm.off3, dm.nk3, dm.nn3, wave,
                   4, ntiles, lane);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -307,7 +312,7 @@ template <int MT, int NTW, bool CNF>
 size_t mfma_smem(int din) {
   constexpr int RT = 16 * MT, PR = CNF ? 8 : RT, H = NTW * 64;
   const Dims dm = dims(din, H);
-  return sizeof(uint16_t) * 2 * ((size_t)RT * (dm.K1 + 8) + RT * (H + 8)) +
+  return sizeof(uint16_t) * 3 * ((size_t)RT * (dm.K1 + 8) + RT * (H + 8)) +
          sizeof(float) * (PR + PR * dm.nn3);
 }
 
@@ -380,12 +385,10 @@ hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s) {
     if (a.H == 256) return launch_t<1, 4, true>(a, s);
     return launch_t<1, 2, true>(a, s);
   }
-  const bool big = row_tile == 32 || (row_tile == 0 && a.B >= 32 * 512);
-  if (a.H == 512) return big ? launch_t<2, 8, false>(a, s)
-                             : launch_t<1, 8, false>(a, s);
-  if (a.H == 256) return big ? launch_t<2, 4, false>(a, s)
-                             : launch_t<1, 4, false>(a, s);
-  return big ? launch_t<2, 2, false>(a, s) : launch_t<1, 2, false>(a, s);
+  (void)row_tile;
+  if (a.H == 512) return launch_t<1, 8, false>(a, s);
+  if (a.H == 256) return launch_t<1, 4, false>(a, s);
+  return launch_t<1, 2, false>(a, s);
 }
 
 }  // namespace bode

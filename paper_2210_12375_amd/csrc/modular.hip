@@ -100,13 +100,19 @@ struct Back {
   R* Ys;           // [7, B, D] stage inputs of step n
   R* Ks;           // [7, B, D] stage values
   R* yseg;         // [k + 1, B, D] states of the current segment
-  R* slots;        // [G, P] per-workgroup parameter-gradient partials
+  R* slots;        // [G, P] split-K partials of the parameter gradient
   int32_t* flags;  // [0]: max accepted steps, [1]: record overflow
+  // Tape of one step, feature-major ([feature][k], k = stage * Bs + row,
+  // Bs = B, or 2B for the CNF whose tangent rows follow the primal ones):
+  // layer inputs with a trailing constant feature (1 on primal rows, 0 on
+  // tangent rows: the bias gradient) and the layer-output cotangents.
+  R *T1in, *T1g, *T2in, *T2g, *T3in, *T3g;
+  long K;  // 7 * Bs
   int32_t cap, k, G;
   long P;
 };
 
-constexpr int kSlots = 64;
+constexpr int kSlots = 16;  // split-K factor of the parameter-gradient GEMMs
 
 inline long n_params(int din, int H) {
   const long n0 = din + 1;
@@ -674,6 +680,14 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     bk.yseg = L.take<R>((size_t)(k + 1) * B * D);
     bk.slots = L.take<R>((size_t)bk.G * bk.P);
     bk.flags = L.take<int32_t>(64);
+    const int H = c.mlp_hidden, n0 = din + 1;
+    bk.K = 7L * (long)B * (c.rhs == BODE_RHS_CNF ? 2 : 1);
+    bk.T1in = L.take<R>((size_t)(n0 + 1) * bk.K);
+    bk.T1g = L.take<R>((size_t)H * bk.K);
+    bk.T2in = L.take<R>((size_t)(H + 1) * bk.K);
+    bk.T2g = L.take<R>((size_t)H * bk.K);
+    bk.T3in = L.take<R>((size_t)(H + 1) * bk.K);
+    bk.T3g = L.take<R>((size_t)din * bk.K);
   }
   MfmaWeights w{};
   if (c.precision == BODE_BF16) {
@@ -1032,8 +1046,8 @@ __global__ void adj_dense(Mod<R> m, Back<R> b, int n, const R* g_eval) {
 }
 
 // mu_s = J_f(Y_s)^T kappa_s for a tile of instances (the field's layers are
-// recomputed in LDS), the parameter gradient added into this workgroup's
-// slot, and the row updates of kappa, lambda.
+// recomputed in LDS), the stage's tape entries for the parameter gradient,
+// and the row updates of kappa, lambda.
 template <typename R, int ROWS>
 __global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
                                                   VjpSpec sp) {
@@ -1056,7 +1070,6 @@ __global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
   R* DG1 = DA2 + ROWS * H;    // dpbar1
   R* DG2 = DG1 + ROWS * H;    // dpbar2
   __shared__ int any;
-  R* slot = b.slots + (long)blockIdx.x * b.P;
   const int s = sp.s;
   const R* Yin = b.Ys + (long)(s - 1) * B * D;
   const R* Kin = b.kap + (long)(s - 1) * B * D;
@@ -1162,42 +1175,44 @@ __global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
       for (int j = 0; j < H; ++j) acc += m.W1[(long)c * H + j] * G1[r * H + j];
       MU[idx] = acc;
     }
-    // parameter gradients into this workgroup's slot (fixed order: no atomics)
-    const long o_b1 = (long)n0 * H, o_W2 = o_b1 + H, o_b2 = o_W2 + (long)H * H;
-    const long o_W3 = o_b2 + H, o_b3 = o_W3 + (long)H * din;
-    for (long p = threadIdx.x; p < b.P; p += blockDim.x) {
-      R v = R(0);
-      if (p < o_b1) {
-        const int i = int(p / H), j = int(p % H);
-        for (int r = 0; r < ROWS; ++r) {
-          v += X[r * n0 + i] * G1[r * H + j];
-          if (cnf && i < din) v += dX[r * n0 + i] * DG1[r * H + j];
-        }
-      } else if (p < o_W2) {
-        const int j = int(p - o_b1);
-        for (int r = 0; r < ROWS; ++r) v += G1[r * H + j];
-      } else if (p < o_b2) {
-        const long q = p - o_W2;
-        const int i = int(q / H), j = int(q % H);
-        for (int r = 0; r < ROWS; ++r) {
-          v += A1[r * H + i] * G2[r * H + j];
-          if (cnf) v += DA1[r * H + i] * DG2[r * H + j];
-        }
-      } else if (p < o_W3) {
-        const int j = int(p - o_b2);
-        for (int r = 0; r < ROWS; ++r) v += G2[r * H + j];
-      } else if (p < o_b3) {
-        const long q = p - o_W3;
-        const int i = int(q / din), j = int(q % din);
-        for (int r = 0; r < ROWS; ++r) {
-          v += A2[r * H + i] * Kp[r * D + j];
-          if (cnf) v += DA2[r * H + i] * (-Kp[r * D + din] * dX[r * n0 + j]);
-        }
-      } else {
-        const int j = int(p - o_b3);
-        for (int r = 0; r < ROWS; ++r) v += Kp[r * D + j];
+    // tape of this stage: layer inputs (+ bias feature) and cotangents
+    {
+      const long Kt = b.K, Bs = cnf ? 2L * B : (long)B;
+      const long kb = (long)(s - 1) * Bs;
+      for (int idx = threadIdx.x; idx < ROWS * (n0 + 1); idx += blockDim.x) {
+        const int r = idx % ROWS, f = idx / ROWS, row = r0 + r;
+        if (row >= B) continue;
+        b.T1in[(long)f * Kt + kb + row] = f < n0 ? X[r * n0 + f] : R(1);
+        if (cnf)
+          b.T1in[(long)f * Kt + kb + B + row] =
+              f < din ? dX[r * n0 + f] : R(0);
       }
-      slot[p] += v;
+      for (int idx = threadIdx.x; idx < ROWS * (H + 1); idx += blockDim.x) {
+        const int r = idx % ROWS, f = idx / ROWS, row = r0 + r;
+        if (row >= B) continue;
+        const long o = (long)f * Kt + kb + row;
+        b.T2in[o] = f < H ? A1[r * H + f] : R(1);
+        b.T3in[o] = f < H ? A2[r * H + f] : R(1);
+        if (f < H) {
+          b.T1g[o] = G1[r * H + f];
+          b.T2g[o] = G2[r * H + f];
+        }
+        if (cnf) {
+          b.T2in[o + B] = f < H ? DA1[r * H + f] : R(0);
+          b.T3in[o + B] = f < H ? DA2[r * H + f] : R(0);
+          if (f < H) {
+            b.T1g[o + B] = DG1[r * H + f];
+            b.T2g[o + B] = DG2[r * H + f];
+          }
+        }
+      }
+      for (int idx = threadIdx.x; idx < ROWS * din; idx += blockDim.x) {
+        const int r = idx % ROWS, f = idx / ROWS, row = r0 + r;
+        if (row >= B) continue;
+        const long o = (long)f * Kt + kb + row;
+        b.T3g[o] = Kp[r * D + f];
+        if (cnf) b.T3g[o + B] = -Kp[r * D + din] * dX[r * n0 + f];
+      }
     }
     __syncthreads();
     // row updates: kappa_j += h a_sj mu (Lambda at stage 7), lambda sums
@@ -1236,7 +1251,7 @@ hipError_t launch_vjp(const Mod<R>& m, const Back<R>& b, const VjpSpec& sp,
   const size_t sm = vjp_smem<R>(rows, n0, m.D, m.H, m.d_in, m.cnf);
   if (sm > 65536) return hipErrorInvalidValue;
   const int ntiles = (m.B + rows - 1) / rows;
-  const dim3 g(ntiles < b.G ? ntiles : b.G), blk(256);
+  const dim3 g(ntiles), blk(256);
   switch (rows) {
     case 8:
       hipLaunchKernelGGL((vjp_kernel<R, 8>), g, blk, sm, s, m, b, sp);
@@ -1263,6 +1278,72 @@ template <typename R>
 __global__ void copy_r(R* dst, const R* src, long n) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+
+// Parameter gradient of one step from its tape: for each layer,
+// C[m][n] += sum_k Tin[m][k] Tg[n][k] over the k range of this split, added
+// into slot[split] (one owner per entry, so the sum is deterministic).  The
+// augmented C = [W; b] of the three layers, concatenated, is dtheta.
+template <typename R>
+__global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
+                                                 long K, int M, int N, int S,
+                                                 R* slots, long P, long off) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ R As[TK][TM + 4];
+  __shared__ R Bs[TK][TN + 4];
+  const int tiles_n = (N + TN - 1) / TN;
+  const int tile = blockIdx.x / S, split = blockIdx.x % S;
+  const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
+  const long kc = ((K + S - 1) / S + TK - 1) / TK * TK;
+  const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  R acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = R(0);
+  for (long kk = k0; kk < k1; kk += TK) {
+    // load TK x 64 of each operand (row m of Tin is contiguous in k)
+    for (int e = threadIdx.x; e < TK * TM; e += 256) {
+      const int kl = e % TK, ml = e / TK;
+      const long k = kk + kl;
+      const int m = m0 + ml, n = n0 + ml;
+      As[kl][ml] = (m < M && k < k1) ? Tin[(long)m * K + k] : R(0);
+      Bs[kl][ml] = (n < N && k < k1) ? Tg[(long)n * K + k] : R(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kl = 0; kl < TK; ++kl) {
+      R a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[kl][ty * 4 + i];
+        bb[i] = Bs[kl][tx * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * bb[j];
+    }
+    __syncthreads();
+  }
+  R* slot = slots + (long)split * P + off;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
+      if (m < M && n < N) slot[(long)m * N + n] += acc[i][j];
+    }
+}
+
+template <typename R>
+hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
+                            int S, R* slots, long P, long off, hipStream_t s) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  hipLaunchKernelGGL(grad_gemm<R>, dim3(tiles * S), dim3(256), 0, s, Tin, Tg,
+                     K, M, N, S, slots, P, off);
+  return hipGetLastError();
 }
 
 // dtheta = sum of the slots in slot order (deterministic).
@@ -1319,6 +1400,12 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   const dim3 rows_g((m.B + 3) / 4), blk(256);
   hipLaunchKernelGGL(fill_r<R>, lin_grid(b.G * b.P), blk, 0, s, b.slots,
                      (long)b.G * b.P, R(0));
+  {  // tape inputs of tiles no step writes must be finite (they meet 0)
+    const long n1 = (long)(m.d_in + 2) * b.K, n2 = (long)(m.H + 1) * b.K;
+    hipLaunchKernelGGL(fill_r<R>, lin_grid(n1), blk, 0, s, b.T1in, n1, R(0));
+    hipLaunchKernelGGL(fill_r<R>, lin_grid(n2), blk, 0, s, b.T2in, n2, R(0));
+    hipLaunchKernelGGL(fill_r<R>, lin_grid(n2), blk, 0, s, b.T3in, n2, R(0));
+  }
   hipLaunchKernelGGL(copy_r<R>, lin_grid(BD), blk, 0, s, b.lam, g_final, BD);
   hipError_t e = launch_fill_i32(b.flags, 2, 0, s);
   if (e != hipSuccess) return e;
@@ -1358,6 +1445,15 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
     e = stages<R, M>(im, v, b, nullptr, true, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval);
+    {  // tape cotangents of skipped (inactive) tiles must read as zero
+      const long H = m.H;
+      hipLaunchKernelGGL(fill_r<R>, lin_grid(H * b.K), blk, 0, s, b.T1g,
+                         H * b.K, R(0));
+      hipLaunchKernelGGL(fill_r<R>, lin_grid(H * b.K), blk, 0, s, b.T2g,
+                         H * b.K, R(0));
+      hipLaunchKernelGGL(fill_r<R>, lin_grid((long)m.d_in * b.K), blk, 0, s,
+                         b.T3g, (long)m.d_in * b.K, R(0));
+    }
     for (int st = 7; st >= 1; --st) {
       VjpSpec sp{};
       sp.s = st;
@@ -1370,6 +1466,19 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
         sp.coef[j] = ss.coef[j];
       }
       e = launch_vjp<R>(m, b, sp, s);
+      if (e != hipSuccess) return e;
+    }
+    {  // parameter gradient of this step
+      const int H = m.H, din = m.d_in, n0 = din + 1;
+      const long o2 = (long)(n0 + 1) * H, o3 = o2 + (long)(H + 1) * H;
+      e = launch_grad_gemm<R>(b.T1in, b.T1g, b.K, n0 + 1, H, b.G, b.slots,
+                              b.P, 0, s);
+      if (e == hipSuccess)
+        e = launch_grad_gemm<R>(b.T2in, b.T2g, b.K, H + 1, H, b.G, b.slots,
+                                b.P, o2, s);
+      if (e == hipSuccess)
+        e = launch_grad_gemm<R>(b.T3in, b.T3g, b.K, H + 1, din, b.G, b.slots,
+                                b.P, o3, s);
       if (e != hipSuccess) return e;
     }
   }
