@@ -60,10 +60,10 @@ __host__ __device__ inline Dims dims(int din, int H) {
   return d;
 }
 
-// Fragment f = kb * nn + nb, lane l, element i holds W[kb*32 + (l/16)*8 + i]
-// [nb*16 + l%16] (zero beyond K rows).
+// Fragment f = kb * nn + nb, lane l, element i holds M[kb*32 + (l/16)*8 + i]
+// [nb*16 + l%16] (zero beyond K rows), where M = W, or W^T when trans.
 __global__ void pack_kernel(uint16_t* dst, const float* W, int K, int ldw,
-                            int nk, int nn) {
+                            int nk, int nn, int trans) {
   const long total = (long)nk * nn * 512;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
@@ -71,8 +71,29 @@ __global__ void pack_kernel(uint16_t* dst, const float* W, int K, int ldw,
     const long f = e >> 9;
     const int kb = int(f / nn), nb = int(f % nn);
     const int k = kb * 32 + (l >> 4) * 8 + i, n = nb * 16 + (l & 15);
-    dst[e] = k < K ? f2bf(W[(long)k * ldw + n]) : uint16_t(0);
+    const long src = trans ? (long)n * ldw + k : (long)k * ldw + n;
+    dst[e] = k < K ? f2bf(W[src]) : uint16_t(0);
   }
+}
+
+// Transposed layers: W3^T [din x H], W2^T [H x H], W1^T [H x din].
+struct DimsT {
+  int nk3, nn3, nk2, nn2, nk1, nn1;
+  size_t off2, off1, total;
+};
+
+__host__ __device__ inline DimsT dims_t(int din, int H) {
+  DimsT d;
+  d.nk3 = (din + 31) / 32;
+  d.nn3 = H / 16;
+  d.nk2 = H / 32;
+  d.nn2 = H / 16;
+  d.nk1 = H / 32;
+  d.nn1 = din / 16;
+  d.off2 = (size_t)d.nk3 * d.nn3 * 512;
+  d.off1 = d.off2 + (size_t)d.nk2 * d.nn2 * 512;
+  d.total = d.off1 + (size_t)d.nk1 * d.nn1 * 512;
+  return d;
 }
 
 __global__ void fvec_kernel(float* f, const float* W1, const float* b1,
@@ -326,12 +347,249 @@ hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// Adjoint stage on MFMA.  The hidden layers are recomputed as in the field
+// kernel; each lane keeps, for its accumulator elements, the activation
+// (primal rows) or the pre-activation tangent (CNF tangent rows), so the
+// backward epilogues need no second pass over LDS.  The backward chain runs
+// the same GEMM on the transposed layers: S2 = gbar W3^T, G2 = tanh'(p2) S2
+// (plus the CNF's second-order term), S1 = G2 W2^T, G1 = tanh'(p1) S1,
+// mu = G1 W1^T.  For the CNF, gbar's tangent rows hold -kappa_l eps, the
+// cotangent of the tangent output.
+template <int NTW, bool CNF>
+__global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
+  constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 64, SA = H + 8;
+  const int din = a.din, D = a.D, B = a.B;
+  const Dims dm = dims(din, H);
+  const DimsT dt = dims_t(din, H);
+  const int SX = dm.K1 + 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int PX = RT * SX, PA = RT * SA;
+  uint16_t* Xh = reinterpret_cast<uint16_t*>(smem_raw);
+  uint16_t* Ah = Xh + 3 * PX;
+  float* tcol = reinterpret_cast<float*>(Ah + 3 * PA);  // [PR]
+  float* MU = reinterpret_cast<float*>(Xh);  // [PR][din], after S2 is read
+  __shared__ int any_running;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.x * PR;
+  if (tid == 0) any_running = 0;
+  __syncthreads();
+  if (tid < PR && r0 + tid < B && a.act[r0 + tid] == kRunning)
+    any_running = 1;
+  __syncthreads();
+  if (!any_running) return;
+  const long K = a.K, kb = a.kb;
+  auto on = [&](int row) { return row < B && a.act[row] == kRunning; };
+
+  // prologue: Y_s and the probe into LDS, the layer-1 inputs into the tape
+  for (int idx = tid; idx < PR * din; idx += blockDim.x) {
+    const int r = idx / din, c = idx % din, row = r0 + r;
+    const bool o = on(row);
+    const float Yv = o ? a.Y[(long)row * D + c] : 0.f;
+    put_split(Xh, PX, r * SX + c, Yv);
+    if (row < B) a.T1in[(long)c * K + kb + row] = Yv;
+    if (CNF) {
+      const float e = o ? a.eps[(long)row * D + c] : 0.f;
+      put_split(Xh, PX, (PR + r) * SX + c, e);
+      if (row < B) a.T1in[(long)c * K + kb + B + row] = e;
+    }
+  }
+  for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
+    const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
+    put_split(Xh, PX, r * SX + c, 0.f);
+  }
+  for (int r = tid; r < PR; r += blockDim.x) {
+    const int row = r0 + r;
+    const float tv =
+        on(row) ? float(a.bt[row] + a.c * double(a.bh[row])) : 0.f;
+    tcol[r] = tv;
+    if (row < B) {
+      a.T1in[(long)din * K + kb + row] = tv;
+      a.T1in[(long)(din + 1) * K + kb + row] = 1.f;
+      if (CNF) {
+        a.T1in[(long)din * K + kb + B + row] = 0.f;
+        a.T1in[(long)(din + 1) * K + kb + B + row] = 0.f;
+      }
+    }
+  }
+  __syncthreads();
+
+  const float* b1 = a.w.fvec;
+  const float* w1t = b1 + H;
+  const float* b2 = b1 + 2 * H;
+  const int rq = (lane >> 4) * 4, col = lane & 15;
+  // tape column of accumulator row `row` of the 16-row tile (-1: none)
+  auto tk = [&](int row) -> long {
+    const bool primal = !CNF || row < PR;
+    const int g = r0 + (primal ? row : row - PR);
+    if (g >= B) return -1;
+    return kb + g + (primal ? 0 : B);
+  };
+
+  float keep[2][NTW][4];
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    f32x4 acc[1][NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (layer == 0)
+      gemm<1, NTW>(acc, Xh, PX, SX, a.w.packed, dm.nk1, dm.nn1, wave * NTW, 1,
+                   NTW, lane);
+    else
+      gemm<1, NTW>(acc, Ah, PA, SA, a.w.packed + dm.off2, dm.nk2, dm.nn2,
+                   wave * NTW, 1, NTW, lane);
+    __syncthreads();
+    const float* bias = layer == 0 ? b1 : b2;
+    float* Tin = layer == 0 ? a.T2in : a.T3in;
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rq + i;
+        float v = acc[0][t][i];
+        const bool primal = !CNF || row < PR;
+        if (primal) {
+          v += bias[n];
+          if (layer == 0) v += tcol[row] * w1t[n];
+        }
+        float act = primal ? tanhf(v) : 0.f;
+        if (CNF) {
+          const float ap = __shfl_xor(act, 32, 64);
+          if (!primal) act = (1.f - ap * ap) * v;
+        }
+        keep[layer][t][i] = primal ? act : v;
+        put_split(Ah, PA, row * SA + n, act);
+        const long k = tk(row);
+        if (k >= 0) Tin[(long)n * K + k] = act;
+      }
+    }
+    __syncthreads();
+  }
+  // bias features of layers 2 and 3 (0 on tangent rows)
+  for (int r = tid; r < RT; r += blockDim.x) {
+    const long k = tk(r);
+    if (k < 0) continue;
+    const float one = (!CNF || r < PR) ? 1.f : 0.f;
+    a.T2in[(long)H * K + k] = one;
+    a.T3in[(long)H * K + k] = one;
+  }
+
+  // gbar: kappa_z on primal rows, -kappa_l eps on tangent rows
+  for (int idx = tid; idx < PR * din; idx += blockDim.x) {
+    const int r = idx / din, c = idx % din, row = r0 + r;
+    const bool o = on(row);
+    const float kz = o ? a.kap_s[(long)row * D + c] : 0.f;
+    put_split(Xh, PX, r * SX + c, kz);
+    if (row < B) a.T3g[(long)c * K + kb + row] = kz;
+    if (CNF) {
+      const float g = o ? -a.kap_s[(long)row * D + din] *
+                              a.eps[(long)row * D + c]
+                        : 0.f;
+      put_split(Xh, PX, (PR + r) * SX + c, g);
+      if (row < B) a.T3g[(long)c * K + kb + B + row] = g;
+    }
+  }
+  __syncthreads();
+
+  // S2 = gbar W3^T, then S1 = G2 W2^T; epilogues form G2, G1
+#pragma unroll
+  for (int layer = 1; layer >= 0; --layer) {
+    f32x4 acc[1][NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (layer == 1)
+      gemm<1, NTW>(acc, Xh, PX, SX, a.w.packedT, dt.nk3, dt.nn3, wave * NTW, 1,
+                   NTW, lane);
+    else
+      gemm<1, NTW>(acc, Ah, PA, SA, a.w.packedT + dt.off2, dt.nk2, dt.nn2,
+                   wave * NTW, 1, NTW, lane);
+    __syncthreads();
+    float* Tg = layer == 1 ? a.T2g : a.T1g;
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rq + i;
+        const float sv = acc[0][t][i], kv = keep[layer][t][i];
+        float g;
+        if (CNF) {
+          const float s_o = __shfl_xor(sv, 32, 64);  // partner row's S
+          const float k_o = __shfl_xor(kv, 32, 64);  // partner's keep
+          if (row < PR)  // primal: a = kv, tangent pre-activation = k_o
+            g = (1.f - kv * kv) * (sv - 2.f * kv * k_o * s_o);
+          else  // tangent: tanh' of the primal row
+            g = (1.f - k_o * k_o) * sv;
+        } else {
+          g = (1.f - kv * kv) * sv;
+        }
+        put_split(Ah, PA, row * SA + n, g);
+        const long k = tk(row);
+        if (k >= 0) Tg[(long)n * K + k] = g;
+      }
+    }
+    __syncthreads();
+  }
+
+  // mu = G1 W1^T (primal rows); column tiles nb = wave, wave + 4, ...
+  {
+    const int ntiles = (dt.nn1 - wave + 3) / 4;
+    f32x4 acc[1][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (ntiles > 0)
+      gemm<1, 4>(acc, Ah, PA, SA, a.w.packedT + dt.off1, dt.nk1, dt.nn1, wave,
+                 4, ntiles, lane);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= ntiles) continue;
+      const int n = (wave + 4 * t) * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rq + i;
+        if (row < PR) MU[row * din + n] = acc[0][t][i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // row updates
+  for (int idx = tid; idx < PR * D; idx += blockDim.x) {
+    const int r = idx / D, c = idx % D, row = r0 + r;
+    if (!on(row)) continue;
+    const float h = a.bh[row];
+    float mu = c < din ? MU[r * din + c] : 0.f;
+    const long o = (long)row * D + c;
+    if (a.s == 7) {
+      mu = a.lam[o] + mu;  // Lambda
+      a.lam[o] = mu;
+    }
+    a.lamn[o] += mu;
+    for (int j = 0; j < a.n; ++j)
+      a.kap[((long)a.kidx[j] * B + row) * D + c] += h * a.coef[j] * mu;
+    if (a.s == 1) a.lam[o] = a.lamn[o];
+  }
+}
+
+template <int NTW, bool CNF>
+hipError_t launch_vjp_t(const MfmaVjpArgs& a, hipStream_t s) {
+  constexpr int PR = CNF ? 8 : 16;
+  const size_t sm = mfma_smem<1, NTW, CNF>(a.din);
+  if (sm > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((vjp_mfma_kernel<NTW, CNF>), dim3((a.B + PR - 1) / PR),
+                     dim3(256), sm, s, a);
+  return hipGetLastError();
+}
 }  // namespace
 
 size_t mfma_packed_elems(int din, int H) {
   const Dims d = dims(din, H);
   return d.off3 + (size_t)d.nk3 * d.nn3 * 512;
 }
+
+size_t mfma_packedT_elems(int din, int H) { return dims_t(din, H).total; }
 
 size_t mfma_fvec_elems(int din, int H) { return 3 * (size_t)H + din; }
 
@@ -349,11 +607,20 @@ hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
                              hipStream_t s) {
   const Dims d = dims(din, H);
   hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, w.packed, W1,
-                     din, H, d.nk1, d.nn1);
+                     din, H, d.nk1, d.nn1, 0);
   hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
-                     w.packed + d.off2, W2, H, H, d.nk2, d.nn2);
+                     w.packed + d.off2, W2, H, H, d.nk2, d.nn2, 0);
   hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
-                     w.packed + d.off3, W3, H, din, d.nk3, d.nn3);
+                     w.packed + d.off3, W3, H, din, d.nk3, d.nn3, 0);
+  if (w.packedT != nullptr) {
+    const DimsT t = dims_t(din, H);
+    hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, w.packedT, W3,
+                       din, din, t.nk3, t.nn3, 1);
+    hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
+                       w.packedT + t.off2, W2, H, H, t.nk2, t.nn2, 1);
+    hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
+                       w.packedT + t.off1, W1, H, H, t.nk1, t.nn1, 1);
+  }
   hipLaunchKernelGGL(fvec_kernel, dim3(8), dim3(256), 0, s, w.fvec, W1, b1, b2,
                      b3, din, H);
   return hipGetLastError();
@@ -377,6 +644,18 @@ MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
   a.eps = eps;
   a.w = w;
   return a;
+}
+
+hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s) {
+  if (a.w.packedT == nullptr) return hipErrorInvalidValue;
+  if (a.cnf) {
+    if (a.H == 512) return launch_vjp_t<8, true>(a, s);
+    if (a.H == 256) return launch_vjp_t<4, true>(a, s);
+    return launch_vjp_t<2, true>(a, s);
+  }
+  if (a.H == 512) return launch_vjp_t<8, false>(a, s);
+  if (a.H == 256) return launch_vjp_t<4, false>(a, s);
+  return launch_vjp_t<2, false>(a, s);
 }
 
 hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s) {

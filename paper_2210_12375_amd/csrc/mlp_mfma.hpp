@@ -14,9 +14,13 @@ namespace bode {
 struct MfmaWeights {
   uint16_t* packed = nullptr;
   float* fvec = nullptr;
+  // Transposed layers for the vector-Jacobian products of the adjoint:
+  // W3^T, W2^T and W1^T without its time row (null when not needed).
+  uint16_t* packedT = nullptr;
 };
 
 size_t mfma_packed_elems(int din, int H);
+size_t mfma_packedT_elems(int din, int H);
 size_t mfma_fvec_elems(int din, int H);
 std::string mfma_supported(int din, int H);
 
@@ -49,5 +53,31 @@ MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
 
 // row_tile 0 picks the default for the shape.
 hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s);
+
+// One stage s of the discrete adjoint for a batch of rows: mu_s =
+// J_f(Y_s)^T kappa_s on MFMA (the field's hidden layers recomputed), the
+// stage's entries of the parameter-gradient tape, and the row updates
+// kappa_j += h a_sj mu_s, lambda_next += mu_s (Lambda = lambda + mu at the
+// last stage, lambda = lambda_next after the first).
+struct MfmaVjpArgs {
+  int B, D, din, H, cnf;
+  const int32_t* act;  // rows with kRunning are differentiated
+  const float* Y;      // [B, D] stage input
+  const float* kap_s;  // [B, D] kappa_s
+  const float* eps;    // [B, D] probe (CNF)
+  const float* bh;     // [B] step size
+  const double* bt;    // [B] t_n
+  double c;            // c_s
+  MfmaWeights w;
+  // tape, feature-major [feature][K]; this stage's columns start at kb
+  float *T1in, *T1g, *T2in, *T2g, *T3in, *T3g;
+  long K, kb;
+  int s, n;
+  int kidx[6];
+  float coef[6];
+  float *lam, *lamn, *kap;  // kap: [7, B, D]
+};
+
+hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s);
 
 }  // namespace bode

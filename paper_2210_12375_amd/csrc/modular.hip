@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "analytic.hpp"
 #include "common.hpp"
@@ -694,6 +695,8 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     const size_t n = mfma_packed_elems(din, c.mlp_hidden);
     w.packed = L.take<uint16_t>(n);
     w.fvec = L.take<float>(mfma_fvec_elems(din, c.mlp_hidden));
+    if (c.record_cap > 0)
+      w.packedT = L.take<uint16_t>(mfma_packedT_elems(din, c.mlp_hidden));
   }
   if (m) {
     m->st = st;
@@ -1268,6 +1271,50 @@ hipError_t launch_vjp(const Mod<R>& m, const Back<R>& b, const VjpSpec& sp,
   return hipGetLastError();
 }
 
+// BF16 precision: the stage's VJP on MFMA (BF16 weights, three-way split
+// activations and cotangents, FP32 accumulation); else the FMA kernel.
+template <typename R>
+hipError_t vjp(const ModImpl& im, const Mod<R>& m, const Back<R>& b,
+               const VjpSpec& sp, hipStream_t s) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (im.cfg.precision == BODE_BF16) {
+      MfmaVjpArgs a{};
+      a.B = m.B;
+      a.D = m.D;
+      a.din = m.d_in;
+      a.H = m.H;
+      a.cnf = m.cnf;
+      a.act = b.act;
+      a.Y = b.Ys + (long)(sp.s - 1) * m.B * m.D;
+      a.kap_s = b.kap + (long)(sp.s - 1) * m.B * m.D;
+      a.eps = m.eps;
+      a.bh = b.bh;
+      a.bt = b.bt;
+      a.c = sp.c;
+      a.w = im.mw;
+      a.T1in = b.T1in;
+      a.T1g = b.T1g;
+      a.T2in = b.T2in;
+      a.T2g = b.T2g;
+      a.T3in = b.T3in;
+      a.T3g = b.T3g;
+      a.K = b.K;
+      a.kb = (long)(sp.s - 1) * (m.cnf ? 2L * m.B : (long)m.B);
+      a.s = sp.s;
+      a.n = sp.n;
+      for (int j = 0; j < sp.n; ++j) {
+        a.kidx[j] = sp.kidx[j];
+        a.coef[j] = float(sp.coef[j]);
+      }
+      a.lam = b.lam;
+      a.lamn = b.lamn;
+      a.kap = b.kap;
+      return launch_vjp_mfma(a, s);
+    }
+  }
+  return launch_vjp<R>(m, b, sp, s);
+}
+
 template <typename R>
 __global__ void fill_r(R* p, long n, R v) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -1337,12 +1384,81 @@ __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
     }
 }
 
+// FP32 tapes: the same product on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32: exact FP32 products, FP32 accumulation).  A
+// 64 x 64 tile of C per workgroup, 32 x 32 per wavefront; both operands
+// staged through LDS 32 k-columns at a time (rows contiguous in k).
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void grad_gemm_mfma(
+    const float* Tin, const float* Tg, long K, int M, int N, int S,
+    float* slots, long P, long off) {
+  constexpr int TK = 32, LD = TK + 1;
+  __shared__ float As[64 * LD];
+  __shared__ float Bs[64 * LD];
+  const int tiles_n = (N + 63) / 64;
+  const int tile = blockIdx.x / S, split = blockIdx.x % S;
+  const int m0 = (tile / tiles_n) * 64, n0 = (tile % tiles_n) * 64;
+  const long kc = ((K + S - 1) / S + TK - 1) / TK * TK;
+  const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (long kk = k0; kk < k1; kk += TK) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q, row = e / TK, kl = e % TK;
+      const long k = kk + kl;
+      const int m = m0 + row, n = n0 + row;
+      As[row * LD + kl] = (m < M && k < k1) ? Tin[(long)m * K + k] : 0.f;
+      Bs[row * LD + kl] = (n < N && k < k1) ? Tg[(long)n * K + k] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < TK; k4 += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[(wm + i * 16 + lr) * LD + k4 + lk];
+        b[i] = Bs[(wn + i * 16 + lr) * LD + k4 + lk];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* slot = slots + (long)split * P + off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + i * 16 + lk * 4 + v;
+        const int n = n0 + wn + j * 16 + lr;
+        if (m < M && n < N) slot[(long)m * N + n] += acc[i][j][v];
+      }
+}
+
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int S, R* slots, long P, long off, hipStream_t s) {
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  hipLaunchKernelGGL(grad_gemm<R>, dim3(tiles * S), dim3(256), 0, s, Tin, Tg,
-                     K, M, N, S, slots, P, off);
+  if constexpr (std::is_same<R, float>::value)
+    hipLaunchKernelGGL(grad_gemm_mfma, dim3(tiles * S), dim3(256), 0, s, Tin,
+                       Tg, K, M, N, S, slots, P, off);
+  else
+    hipLaunchKernelGGL(grad_gemm<R>, dim3(tiles * S), dim3(256), 0, s, Tin, Tg,
+                       K, M, N, S, slots, P, off);
   return hipGetLastError();
 }
 
@@ -1465,7 +1581,7 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
         sp.kidx[j] = ss.kidx[j];
         sp.coef[j] = ss.coef[j];
       }
-      e = launch_vjp<R>(m, b, sp, s);
+      e = vjp<R>(im, m, b, sp, s);
       if (e != hipSuccess) return e;
     }
     {  // parameter gradient of this step
