@@ -101,6 +101,11 @@ typedef struct {
    * controller would propose next, given the replayed decisions so far.    */
   double* err_rec;
   double* hprop_rec;
+  /* Rounding probe for the tests (not part of the method): when nonzero the
+   * state is rounded to the nearest float after every accepted step, which
+   * shows how strongly the trajectory amplifies float-sized perturbations
+   * made at every step.                                                    */
+  int32_t round_state_f32;
 } orc_options;
 
 /* Solves every instance.  Outputs:

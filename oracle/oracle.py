@@ -44,7 +44,7 @@ class _Options(C.Structure):
                 ("h_replay", _dp), ("n_replay", _ip), ("replay_cap", C.c_int32),
                 ("replay_final", _ip),
                 ("h_rec", _dp), ("rec_cap", C.c_int32), ("err_rec", _dp),
-                ("hprop_rec", _dp)]
+                ("hprop_rec", _dp), ("round_state_f32", C.c_int32)]
 
 
 def _load(variant=None):
@@ -135,15 +135,17 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
           beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2, fac_max=10.0,
           max_steps=100000, n_threads=0, h_replay=None, n_replay=None,
           record_cap=0, replay_errors=False, variant=None,
-          replay_final=None):
+          replay_final=None, round_state_f32=False):
     """Solves every instance; returns a dict of numpy arrays.
 
     variant="fma" runs the same source compiled with contracted multiply-adds
-    (a rounding probe for the tests, not a reference)."""
+    and round_state_f32=True rounds the state to float after every accepted
+    step (rounding probes for the tests, not references)."""
     lib = _load(variant)
     m = _Marshalled(problem)
     o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
                  n_threads)
+    o.round_state_f32 = int(bool(round_state_f32))
     if h_replay is not None:
         h_replay = _f64(h_replay)
         n_replay = np.ascontiguousarray(n_replay, dtype=np.int32)

@@ -249,6 +249,8 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
         }
         t = tnew;
         memcpy(y, ynew, sizeof(double) * n);
+        if (O->round_state_f32)
+          for (int c = 0; c < n; ++c) y[c] = (double)(float)y[c];
         memcpy(k[0], k[6], sizeof(double) * n); /* FSAL */
         err_prev = fmax(err, 1e-4);
         nacc += 1;

@@ -295,6 +295,8 @@ __device__ __forceinline__ int fetch(const AnalyticArgs<R>& a, int kind) {
   return kind == kKindVdp ? a.list[p] : a.list[a.B - 1 - p];
 }
 
+constexpr int kLongRun = 256;
+
 template <typename R, class M, class F, bool REC, bool KEEP>
 __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
                                                     int kind) {
@@ -309,6 +311,10 @@ __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
       while (L.status == kRunning && used < a.budget) {
         attempt<R, M, F, REC, KEEP>(a, L, f);
         ++used;
+        // An instance still stepping after many attempts is on the batch's
+        // critical path (the solve ends with its last step): its wavefront
+        // issues ahead of the short-lived ones sharing the SIMD.
+        if (used == kLongRun) __builtin_amdgcn_s_setprio(3);
       }
       if (L.status == kRunning)
         store_lane(a, L);

@@ -1,4 +1,10 @@
-// Neural right-hand sides on BF16 MFMA (gfx950 v_mfma_f32_16x16x32_bf16).
+// Neural right-hand sides on the matrix cores of gfx950.
+//
+// Two operand policies share the kernels.  BF16 mode (Bf3):
+// v_mfma_f32_16x16x32_bf16 with BF16 weights and split activations, as
+// described below.  FP32 mode (F32): v_mfma_f32_16x16x4_f32 with FP32
+// weights and activations (each 32-wide k block is eight 4-wide products
+// over the same lane layout, so packing and LDS addressing are shared).
 //
 // One workgroup (4 wavefronts) evaluates the field for a tile of instances.
 // Its prologue forms each instance's stage input Y = y + h sum_j a_sj k_j in
@@ -62,8 +68,12 @@ __host__ __device__ inline Dims dims(int din, int H) {
 
 // Fragment f = kb * nn + nb, lane l, element i holds M[kb*32 + (l/16)*8 + i]
 // [nb*16 + l%16] (zero beyond K rows), where M = W, or W^T when trans.
-__global__ void pack_kernel(uint16_t* dst, const float* W, int K, int ldw,
-                            int nk, int nn, int trans) {
+__device__ __forceinline__ void cvt(uint16_t& d, float v) { d = f2bf(v); }
+__device__ __forceinline__ void cvt(float& d, float v) { d = v; }
+
+template <typename W>
+__global__ void pack_kernel(W* dst, const float* Wm, int K, int ldw, int nk,
+                            int nn, int trans) {
   const long total = (long)nk * nn * 512;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
@@ -72,7 +82,7 @@ __global__ void pack_kernel(uint16_t* dst, const float* W, int K, int ldw,
     const int kb = int(f / nn), nb = int(f % nn);
     const int k = kb * 32 + (l >> 4) * 8 + i, n = nb * 16 + (l & 15);
     const long src = trans ? (long)n * ldw + k : (long)k * ldw + n;
-    dst[e] = k < K ? f2bf(W[src]) : uint16_t(0);
+    cvt(dst[e], k < K ? Wm[src] : 0.f);
   }
 }
 
@@ -125,45 +135,6 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
-// B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit at
-// Ah, Ah + plane, Ah + 2 plane.
-template <int MT, int NTW>
-__device__ __forceinline__ void gemm(f32x4 (&acc)[MT][NTW], const uint16_t* Ah,
-                                     int plane, int lda, const uint16_t* Bp,
-                                     int nk, int nn, int nb0, int nstep,
-                                     int ntiles, int lane) {
-  const int r = lane & 15, kq = (lane >> 4) * 8;
-  for (int kb = 0; kb < nk; ++kb) {
-    bf16x8 ah[MT], am[MT], al[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int off = (mt * 16 + r) * lda + kb * 32 + kq;
-      ah[mt] = lds8(Ah + off);
-      am[mt] = lds8(Ah + plane + off);
-      al[mt] = lds8(Ah + 2 * plane + off);
-    }
-    bf16x8 bfrag[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-      const int nb = nb0 + t * nstep;
-      if (t < ntiles)
-        bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb) * 64 + lane) * 8);
-    }
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-      if (t < ntiles) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          acc[mt][t] = mfma(al[mt], bfrag[t], acc[mt][t]);
-          acc[mt][t] = mfma(am[mt], bfrag[t], acc[mt][t]);
-          acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
-        }
-      }
-    }
-  }
-}
-
 // v = hi + mid + lo in bf16 (terms at Ah, Ah + plane, Ah + 2 plane).
 __device__ __forceinline__ void put_split(uint16_t* Ah, int plane, int off,
                                           float v) {
@@ -175,23 +146,152 @@ __device__ __forceinline__ void put_split(uint16_t* Ah, int plane, int off,
   Ah[2 * plane + off] = f2bf(r1 - bf2f(m));
 }
 
+struct Bf3 {
+  typedef uint16_t W;  // packed weight element
+  typedef uint16_t A;  // LDS activation element
+  static constexpr int kPlanes = 3, kPad = 8;
+  __device__ static __forceinline__ void put(A* p, int plane, int off,
+                                             float v) {
+    put_split(p, plane, off, v);
+  }
+  // C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
+  // B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit
+  // at Ah, Ah + plane, Ah + 2 plane.  The B fragments of block kb + 1 are
+  // in flight while block kb is multiplied.
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
+                                              const A* Ah, int plane, int lda,
+                                              const W* Bp, int nk, int nn,
+                                              int nb0, int nstep, int ntiles,
+                                              int lane) {
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    bf16x8 cur[NTW], nxt[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t)
+      if (t < ntiles)
+        cur[t] = gld8(Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8);
+    for (int kb = 0; kb < nk; ++kb) {
+      if (kb + 1 < nk) {
+#pragma unroll
+        for (int t = 0; t < NTW; ++t)
+          if (t < ntiles)
+            nxt[t] = gld8(
+                Bp + ((size_t)((kb + 1) * nn + nb0 + t * nstep) * 64 + lane) * 8);
+      }
+      bf16x8 ah[MT], am[MT], al[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int off = (mt * 16 + r) * lda + kb * 32 + kq;
+        ah[mt] = lds8(Ah + off);
+        am[mt] = lds8(Ah + plane + off);
+        al[mt] = lds8(Ah + 2 * plane + off);
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (t < ntiles) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][t] = mfma(al[mt], cur[t], acc[mt][t]);
+            acc[mt][t] = mfma(am[mt], cur[t], acc[mt][t]);
+            acc[mt][t] = mfma(ah[mt], cur[t], acc[mt][t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) cur[t] = nxt[t];
+    }
+  }
+};
+
+// FP32 policy: A and B fragments are 8 FP32 values per lane; product q of
+// a 32-wide k block takes element q of both (the 4 k indices of one
+// 16x16x4 product are kb*32 + g*8 + q, g = lane / 16).
+struct F32 {
+  typedef float W;
+  typedef float A;
+  static constexpr int kPlanes = 1, kPad = 4;
+  __device__ static __forceinline__ void put(A* p, int, int off, float v) {
+    p[off] = v;
+  }
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
+                                              const A* Ah, int, int lda,
+                                              const W* Bp, int nk, int nn,
+                                              int nb0, int nstep, int ntiles,
+                                              int lane) {
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 c0[NTW], c1[NTW], n0[NTW], n1[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      if (t < ntiles) {
+        const W* q = Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8;
+        c0[t] = *reinterpret_cast<const f32x4*>(q);
+        c1[t] = *reinterpret_cast<const f32x4*>(q + 4);
+      }
+    }
+    for (int kb = 0; kb < nk; ++kb) {
+      if (kb + 1 < nk) {
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+          if (t < ntiles) {
+            const W* q =
+                Bp + ((size_t)((kb + 1) * nn + nb0 + t * nstep) * 64 + lane) * 8;
+            n0[t] = *reinterpret_cast<const f32x4*>(q);
+            n1[t] = *reinterpret_cast<const f32x4*>(q + 4);
+          }
+        }
+      }
+      f32x4 a0[MT], a1[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const A* p = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
+        a0[mt] = *reinterpret_cast<const f32x4*>(p);
+        a1[mt] = *reinterpret_cast<const f32x4*>(p + 4);
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (t < ntiles) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  a0[mt][q], c0[t][q], acc[mt][t], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  a1[mt][q], c1[t][q], acc[mt][t], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        c0[t] = n0[t];
+        c1[t] = n1[t];
+      }
+    }
+  }
+};
+
 // MT 16-row tiles per workgroup (MLP: 16 MT instances; CNF: MT = 1 holds
 // 8 instances and their 8 tangent rows); NTW = H / 64 column tiles per
 // wavefront in the hidden layers.
-template <int MT, int NTW, bool CNF>
+template <class Op, int MT, int NTW, bool CNF>
 __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
+  typedef typename Op::A A;
+  typedef typename Op::W W;
   constexpr int RT = 16 * MT;
   constexpr int PR = CNF ? 8 : RT;  // instances per workgroup
   constexpr int H = NTW * 64;
-  constexpr int SA = H + 8;  // LDS row stride of activations (bank spread)
+  constexpr int SA = H + Op::kPad;  // LDS row stride (bank spread)
   const int din = a.din, D = a.D, B = a.B;
   const Dims dm = dims(din, H);
-  const int SX = dm.K1 + 8;
+  const int SX = dm.K1 + Op::kPad;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int PX = RT * SX, PA = RT * SA;  // split-term planes
-  uint16_t* Xh = reinterpret_cast<uint16_t*>(smem_raw);
-  uint16_t* Ah = Xh + 3 * PX;
-  float* tcol = reinterpret_cast<float*>(Ah + 3 * PA);  // [PR]
+  A* Xh = reinterpret_cast<A*>(smem_raw);
+  A* Ah = Xh + Op::kPlanes * PX;
+  float* tcol = reinterpret_cast<float*>(Ah + Op::kPlanes * PA);  // [PR]
   float* red = tcol + PR;                                 // [PR][nn3]
   __shared__ int any_running;
 
@@ -215,17 +315,17 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
       Yv = a.y[(long)row * D + c] + a.hs[row] * acc;
       if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
     }
-    if (c < din) put_split(Xh, PX, r * SX + c, Yv);
+    if (c < din) Op::put(Xh, PX, r * SX + c, Yv);
   }
   for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
     const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
-    put_split(Xh, PX, r * SX + c, 0.f);
+    Op::put(Xh, PX, r * SX + c, 0.f);
   }
   if (CNF) {
     for (int idx = tid; idx < PR * din; idx += blockDim.x) {
       const int r = idx / din, c = idx % din, row = r0 + r;
       const float e = row < B ? a.eps[(long)row * D + c] : 0.f;
-      put_split(Xh, PX, (PR + r) * SX + c, e);
+      Op::put(Xh, PX, (PR + r) * SX + c, e);
     }
   }
   for (int r = tid; r < PR; r += blockDim.x) {
@@ -248,10 +348,10 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
 #pragma unroll
       for (int t = 0; t < NTW; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 0)
-      gemm<MT, NTW>(acc, Xh, PX, SX, a.w.packed, dm.nk1, dm.nn1, wave * NTW, 1,
+      Op::template gemm<MT, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
                     NTW, lane);
     else
-      gemm<MT, NTW>(acc, Ah, PA, SA, a.w.packed + dm.off2, dm.nk2, dm.nn2,
+      Op::template gemm<MT, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
                     wave * NTW, 1, NTW, lane);
     __syncthreads();  // every wave has read its layer input
     const float* bias = layer == 0 ? b1 : b2;
@@ -274,7 +374,7 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
             const float ap = __shfl_xor(act, 32, 64);  // primal of row - 8
             if (!primal) act = (1.f - ap * ap) * v;
           }
-          put_split(Ah, PA, row * SA + n, act);
+          Op::put(Ah, PA, row * SA + n, act);
         }
       }
     __syncthreads();
@@ -289,7 +389,7 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
-      gemm<MT, 4>(acc, Ah, PA, SA, a.w.packed + dm.off3, dm.nk3, dm.nn3, wave,
+      Op::template gemm<MT, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off3, dm.nk3, dm.nn3, wave,
                   4, ntiles, lane);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -329,20 +429,21 @@ __global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
   }
 }
 
-template <int MT, int NTW, bool CNF>
+template <class Op, int MT, int NTW, bool CNF>
 size_t mfma_smem(int din) {
   constexpr int RT = 16 * MT, PR = CNF ? 8 : RT, H = NTW * 64;
   const Dims dm = dims(din, H);
-  return sizeof(uint16_t) * 3 * ((size_t)RT * (dm.K1 + 8) + RT * (H + 8)) +
+  return sizeof(typename Op::A) * Op::kPlanes *
+             ((size_t)RT * (dm.K1 + Op::kPad) + RT * (H + Op::kPad)) +
          sizeof(float) * (PR + PR * dm.nn3);
 }
 
-template <int MT, int NTW, bool CNF>
+template <class Op, int MT, int NTW, bool CNF>
 hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16 * MT;
-  const size_t sm = mfma_smem<MT, NTW, CNF>(a.din);
+  const size_t sm = mfma_smem<Op, MT, NTW, CNF>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((field_mfma_kernel<MT, NTW, CNF>),
+  hipLaunchKernelGGL((field_mfma_kernel<Op, MT, NTW, CNF>),
                      dim3((a.B + PR - 1) / PR), dim3(256), sm, s, a);
   return hipGetLastError();
 }
@@ -356,18 +457,20 @@ hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
 // (plus the CNF's second-order term), S1 = G2 W2^T, G1 = tanh'(p1) S1,
 // mu = G1 W1^T.  For the CNF, gbar's tangent rows hold -kappa_l eps, the
 // cotangent of the tangent output.
-template <int NTW, bool CNF>
+template <class Op, int NTW, bool CNF>
 __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
-  constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 64, SA = H + 8;
+  typedef typename Op::A A;
+  typedef typename Op::W W;
+  constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 64, SA = H + Op::kPad;
   const int din = a.din, D = a.D, B = a.B;
   const Dims dm = dims(din, H);
   const DimsT dt = dims_t(din, H);
-  const int SX = dm.K1 + 8;
+  const int SX = dm.K1 + Op::kPad;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int PX = RT * SX, PA = RT * SA;
-  uint16_t* Xh = reinterpret_cast<uint16_t*>(smem_raw);
-  uint16_t* Ah = Xh + 3 * PX;
-  float* tcol = reinterpret_cast<float*>(Ah + 3 * PA);  // [PR]
+  A* Xh = reinterpret_cast<A*>(smem_raw);
+  A* Ah = Xh + Op::kPlanes * PX;
+  float* tcol = reinterpret_cast<float*>(Ah + Op::kPlanes * PA);  // [PR]
   float* MU = reinterpret_cast<float*>(Xh);  // [PR][din], after S2 is read
   __shared__ int any_running;
 
@@ -387,17 +490,17 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     const int r = idx / din, c = idx % din, row = r0 + r;
     const bool o = on(row);
     const float Yv = o ? a.Y[(long)row * D + c] : 0.f;
-    put_split(Xh, PX, r * SX + c, Yv);
+    Op::put(Xh, PX, r * SX + c, Yv);
     if (row < B) a.T1in[(long)c * K + kb + row] = Yv;
     if (CNF) {
       const float e = o ? a.eps[(long)row * D + c] : 0.f;
-      put_split(Xh, PX, (PR + r) * SX + c, e);
+      Op::put(Xh, PX, (PR + r) * SX + c, e);
       if (row < B) a.T1in[(long)c * K + kb + B + row] = e;
     }
   }
   for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
     const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
-    put_split(Xh, PX, r * SX + c, 0.f);
+    Op::put(Xh, PX, r * SX + c, 0.f);
   }
   for (int r = tid; r < PR; r += blockDim.x) {
     const int row = r0 + r;
@@ -434,10 +537,10 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 0)
-      gemm<1, NTW>(acc, Xh, PX, SX, a.w.packed, dm.nk1, dm.nn1, wave * NTW, 1,
+      Op::template gemm<1, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
                    NTW, lane);
     else
-      gemm<1, NTW>(acc, Ah, PA, SA, a.w.packed + dm.off2, dm.nk2, dm.nn2,
+      Op::template gemm<1, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
                    wave * NTW, 1, NTW, lane);
     __syncthreads();
     const float* bias = layer == 0 ? b1 : b2;
@@ -460,7 +563,7 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
           if (!primal) act = (1.f - ap * ap) * v;
         }
         keep[layer][t][i] = primal ? act : v;
-        put_split(Ah, PA, row * SA + n, act);
+        Op::put(Ah, PA, row * SA + n, act);
         const long k = tk(row);
         if (k >= 0) Tin[(long)n * K + k] = act;
       }
@@ -481,13 +584,13 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     const int r = idx / din, c = idx % din, row = r0 + r;
     const bool o = on(row);
     const float kz = o ? a.kap_s[(long)row * D + c] : 0.f;
-    put_split(Xh, PX, r * SX + c, kz);
+    Op::put(Xh, PX, r * SX + c, kz);
     if (row < B) a.T3g[(long)c * K + kb + row] = kz;
     if (CNF) {
       const float g = o ? -a.kap_s[(long)row * D + din] *
                               a.eps[(long)row * D + c]
                         : 0.f;
-      put_split(Xh, PX, (PR + r) * SX + c, g);
+      Op::put(Xh, PX, (PR + r) * SX + c, g);
       if (row < B) a.T3g[(long)c * K + kb + B + row] = g;
     }
   }
@@ -500,10 +603,10 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 1)
-      gemm<1, NTW>(acc, Xh, PX, SX, a.w.packedT, dt.nk3, dt.nn3, wave * NTW, 1,
+      Op::template gemm<1, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packedT), dt.nk3, dt.nn3, wave * NTW, 1,
                    NTW, lane);
     else
-      gemm<1, NTW>(acc, Ah, PA, SA, a.w.packedT + dt.off2, dt.nk2, dt.nn2,
+      Op::template gemm<1, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off2, dt.nk2, dt.nn2,
                    wave * NTW, 1, NTW, lane);
     __syncthreads();
     float* Tg = layer == 1 ? a.T2g : a.T1g;
@@ -525,7 +628,7 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
         } else {
           g = (1.f - kv * kv) * sv;
         }
-        put_split(Ah, PA, row * SA + n, g);
+        Op::put(Ah, PA, row * SA + n, g);
         const long k = tk(row);
         if (k >= 0) Tg[(long)n * K + k] = g;
       }
@@ -540,7 +643,7 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
-      gemm<1, 4>(acc, Ah, PA, SA, a.w.packedT + dt.off1, dt.nk1, dt.nn1, wave,
+      Op::template gemm<1, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
                  4, ntiles, lane);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -573,31 +676,80 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
   }
 }
 
-template <int NTW, bool CNF>
+template <class Op, int NTW, bool CNF>
 hipError_t launch_vjp_t(const MfmaVjpArgs& a, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
-  const size_t sm = mfma_smem<1, NTW, CNF>(a.din);
+  const size_t sm = mfma_smem<Op, 1, NTW, CNF>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((vjp_mfma_kernel<NTW, CNF>), dim3((a.B + PR - 1) / PR),
+  hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF>), dim3((a.B + PR - 1) / PR),
                      dim3(256), sm, s, a);
   return hipGetLastError();
 }
-}  // namespace
 
-size_t mfma_packed_elems(int din, int H) {
+template <class Op>
+hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
+                    const float* W2, const float* W3, hipStream_t s) {
+  typedef typename Op::W W;
   const Dims d = dims(din, H);
-  return d.off3 + (size_t)d.nk3 * d.nn3 * 512;
+  W* p = static_cast<W*>(w.packed);
+  hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, p, W1, din,
+                     H, d.nk1, d.nn1, 0);
+  hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, p + d.off2,
+                     W2, H, H, d.nk2, d.nn2, 0);
+  hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, p + d.off3,
+                     W3, H, din, d.nk3, d.nn3, 0);
+  if (w.packedT != nullptr) {
+    const DimsT t = dims_t(din, H);
+    W* q = static_cast<W*>(w.packedT);
+    hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, q, W3, din,
+                       din, t.nk3, t.nn3, 1);
+    hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, q + t.off2,
+                       W2, H, H, t.nk2, t.nn2, 1);
+    hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, q + t.off1,
+                       W1, H, H, t.nk1, t.nn1, 1);
+  }
+  return hipGetLastError();
 }
 
-size_t mfma_packedT_elems(int din, int H) { return dims_t(din, H).total; }
+template <class Op, bool CNF>
+hipError_t field_h(const MfmaArgs& a, hipStream_t s) {
+  switch (a.H) {
+    case 512: return launch_t<Op, 1, 8, CNF>(a, s);
+    case 256: return launch_t<Op, 1, 4, CNF>(a, s);
+    case 128: return launch_t<Op, 1, 2, CNF>(a, s);
+    default: return launch_t<Op, 1, 1, CNF>(a, s);
+  }
+}
+
+template <class Op, bool CNF>
+hipError_t vjp_h(const MfmaVjpArgs& a, hipStream_t s) {
+  switch (a.H) {
+    case 512: return launch_vjp_t<Op, 8, CNF>(a, s);
+    case 256: return launch_vjp_t<Op, 4, CNF>(a, s);
+    case 128: return launch_vjp_t<Op, 2, CNF>(a, s);
+    default: return launch_vjp_t<Op, 1, CNF>(a, s);
+  }
+}
+
+}  // namespace
+
+size_t mfma_packed_bytes(int din, int H, int f32) {
+  const Dims d = dims(din, H);
+  return (d.off3 + (size_t)d.nk3 * d.nn3 * 512) * (f32 ? 4 : 2);
+}
+
+size_t mfma_packedT_bytes(int din, int H, int f32) {
+  return dims_t(din, H).total * (f32 ? 4 : 2);
+}
 
 size_t mfma_fvec_elems(int din, int H) { return 3 * (size_t)H + din; }
 
 std::string mfma_supported(int din, int H) {
   if (din < 16 || din % 16 != 0 || din > 256)
-    return "BF16 fields need a state width that is a multiple of 16, <= 256";
-  if (H != 128 && H != 256 && H != 512)
-    return "BF16 fields are built for hidden widths 128, 256 and 512";
+    return "matrix-core fields need a state width that is a multiple of 16, "
+           "<= 256";
+  if (H != 64 && H != 128 && H != 256 && H != 512)
+    return "matrix-core fields are built for hidden widths 64, 128, 256, 512";
   return "";
 }
 
@@ -605,22 +757,9 @@ hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
                              const float* W1, const float* b1, const float* W2,
                              const float* b2, const float* W3, const float* b3,
                              hipStream_t s) {
-  const Dims d = dims(din, H);
-  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, w.packed, W1,
-                     din, H, d.nk1, d.nn1, 0);
-  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
-                     w.packed + d.off2, W2, H, H, d.nk2, d.nn2, 0);
-  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
-                     w.packed + d.off3, W3, H, din, d.nk3, d.nn3, 0);
-  if (w.packedT != nullptr) {
-    const DimsT t = dims_t(din, H);
-    hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, w.packedT, W3,
-                       din, din, t.nk3, t.nn3, 1);
-    hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
-                       w.packedT + t.off2, W2, H, H, t.nk2, t.nn2, 1);
-    hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s,
-                       w.packedT + t.off1, W1, H, H, t.nk1, t.nn1, 1);
-  }
+  const hipError_t e = w.f32 ? pack_all<F32>(w, din, H, W1, W2, W3, s)
+                             : pack_all<Bf3>(w, din, H, W1, W2, W3, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fvec_kernel, dim3(8), dim3(256), 0, s, w.fvec, W1, b1, b2,
                      b3, din, H);
   return hipGetLastError();
@@ -648,26 +787,16 @@ MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
 
 hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s) {
   if (a.w.packedT == nullptr) return hipErrorInvalidValue;
-  if (a.cnf) {
-    if (a.H == 512) return launch_vjp_t<8, true>(a, s);
-    if (a.H == 256) return launch_vjp_t<4, true>(a, s);
-    return launch_vjp_t<2, true>(a, s);
-  }
-  if (a.H == 512) return launch_vjp_t<8, false>(a, s);
-  if (a.H == 256) return launch_vjp_t<4, false>(a, s);
-  return launch_vjp_t<2, false>(a, s);
+  if (a.w.f32)
+    return a.cnf ? vjp_h<F32, true>(a, s) : vjp_h<F32, false>(a, s);
+  return a.cnf ? vjp_h<Bf3, true>(a, s) : vjp_h<Bf3, false>(a, s);
 }
 
 hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s) {
-  if (a.cnf) {
-    if (a.H == 512) return launch_t<1, 8, true>(a, s);
-    if (a.H == 256) return launch_t<1, 4, true>(a, s);
-    return launch_t<1, 2, true>(a, s);
-  }
   (void)row_tile;
-  if (a.H == 512) return launch_t<1, 8, false>(a, s);
-  if (a.H == 256) return launch_t<1, 4, false>(a, s);
-  return launch_t<1, 2, false>(a, s);
+  if (a.w.f32)
+    return a.cnf ? field_h<F32, true>(a, s) : field_h<F32, false>(a, s);
+  return a.cnf ? field_h<Bf3, true>(a, s) : field_h<Bf3, false>(a, s);
 }
 
 }  // namespace bode

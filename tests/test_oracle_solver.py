@@ -353,3 +353,20 @@ def test_replay_reproduces_the_adaptive_solve():
     nxt = np.abs(r["h_rec"][:, 1:cap])
     ok = valid[:, 1:] & (nxt < prop * (1 - 1e-12))  # clipped final steps
     assert np.all((np.abs(nxt - prop) <= 1e-15 * prop)[valid[:, 1:] & ~ok])
+
+
+def test_float_rounding_probe_is_float_sized():
+    """The tests' rounding probe (state rounded to float after each accepted
+    step) perturbs a well-conditioned replay by float-sized amounts and leaves
+    the step sequence alone."""
+    p = W.vdp_batch(B=16)
+    r = oracle.solve(p, method="dopri5", record_cap=2048)
+    n = r["n_attempted"]
+    h = r["h_rec"][:, :n.max()]
+    rr = oracle.solve(p, method="dopri5", h_replay=h, n_replay=n)
+    rp = oracle.solve(p, method="dopri5", h_replay=h, n_replay=n,
+                      round_state_f32=True)
+    np.testing.assert_array_equal(rp["n_accepted"], rr["n_accepted"])
+    rel = np.abs(rp["y_final"] - rr["y_final"]).max(axis=1) / \
+        np.abs(rr["y_final"]).max(axis=1)
+    assert np.all(rel > 1e-12) and np.all(rel < 1e-4), rel
