@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "analytic.hpp"
 #include "common.hpp"
@@ -79,7 +80,9 @@ template <typename R, int N>
 struct Lane {
   R y[N];
   R k[7][N];
-  double t, te, next_te;
+  // next_te is the instance's next evaluation time, next_te2 the one after:
+  // it is fetched one emission early, so an emission never waits on memory.
+  double t, te, next_te, next_te2;
   R h, err_prev, rtol, atol;
   int32_t n_att, n_acc, n_rej, n_fe, status, cursor, prev_rej, dim, inst;
 };
@@ -90,6 +93,17 @@ __device__ __forceinline__ void write_row(R* row, int D, const R* v, int dim) {
   for (int q = 0; q < N; ++q)
     if (q < D) row[q] = q < dim ? v[q] : R(0);
   for (int q = N; q < D; ++q) row[q] = R(0);
+}
+
+// Columns [0, N) only: the padding columns [N, D) of the evaluation rows
+// are written once, at initialisation, so an emission stores only what
+// the field computes.
+template <typename R, int N>
+__device__ __forceinline__ void write_row_n(R* row, int D, const R* v,
+                                            int dim) {
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (q < D) row[q] = q < dim ? v[q] : R(0);
 }
 
 template <typename R, int N>
@@ -116,6 +130,8 @@ __device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<
   L.cursor = s.cursor[i];
   L.prev_rej = s.prev_rej[i];
   L.next_te = L.cursor < a.E ? a.t_eval[(long)i * a.E + L.cursor] : INFINITY;
+  L.next_te2 =
+      L.cursor + 1 < a.E ? a.t_eval[(long)i * a.E + L.cursor + 1] : INFINITY;
   const R* yr = s.y + (long)i * a.D;
   const R* kr = s.k1 + (long)i * a.D;
 #pragma unroll
@@ -201,7 +217,12 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
     const R r = ctl_div(eq, sc);
     if (N == 2 || q < L.dim) acc += r * r;
   }
-  const R err = ctl_sqrt(N == 2 ? acc * R(0.5) : ctl_div(acc, R(L.dim)));
+  // err^2 (mean of the squares); FP64 takes the root as written, FP32 works
+  // with the square: err < 1 iff err^2 < 1, and both powers of the
+  // controller come from one log2(err^2)
+  const R err2 = N == 2 ? acc * R(0.5) : ctl_div(acc, R(L.dim));
+  constexpr bool kSq = std::is_same<R, float>::value;
+  const R err = kSq ? err2 : ctl_sqrt(err2);
   const bool accept = err < R(1);
   if (REC && L.n_att <= a.rec_cap)
     a.h_rec[(long)L.inst * a.rec_cap + L.n_att - 1] =
@@ -212,7 +233,13 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
   // non-finite err gives fac_min (err = 0 reaches fac_max through the clamp).
   // L.err_prev holds err_prev^beta2, formed when that step was accepted.
   const Ctrl& c = a.ctrl;
-  const R pw = ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
+  R pw, lg = R(0);
+  if constexpr (kSq) {
+    lg = __builtin_amdgcn_logf(err2);  // log2
+    pw = __builtin_amdgcn_exp2f(lg * (accept ? R(-0.5 * c.beta1) : R(-0.1)));
+  } else {
+    pw = ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
+  }
   R fac = R(c.safety) * pw;
   fac = accept ? fac * L.err_prev : fac;
   fac = rmax(R(c.fac_min), accept ? rmin(R(c.fac_max), fac) : fac);
@@ -224,7 +251,9 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
     // Dense output at this instance's own evaluation times in (t, t_new]
     // (Horner in theta, then the stage combination).
     while (__builtin_expect(L.next_te <= tnew, 0)) {
-      const R th = R((L.next_te - L.t) / double(hs));
+      // theta = (t_e - t_n) / h: the difference in double, the quotient in
+      // the state's precision
+      const R th = ctl_div(R(L.next_te - L.t), hs);
       R w[7];
 #pragma unroll
       for (int j = 0; j < 7; ++j)
@@ -240,12 +269,13 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
           if (dense_uses<M>(j)) s2 += w[j] * L.k[j][q];
         out[q] = L.y[q] + hs * s2;
       }
-      write_row<R, N>(a.y_eval + ((long)L.inst * a.E + L.cursor) * a.D, a.D,
-                      out, L.dim);
+      write_row_n<R, N>(a.y_eval + ((long)L.inst * a.E + L.cursor) * a.D,
+                        a.D, out, L.dim);
       L.cursor += 1;
-      L.next_te = L.cursor < a.E
-                      ? a.t_eval[(long)L.inst * a.E + L.cursor]
-                      : INFINITY;
+      L.next_te = L.next_te2;
+      L.next_te2 = L.cursor + 1 < a.E
+                       ? a.t_eval[(long)L.inst * a.E + L.cursor + 1]
+                       : INFINITY;
     }
     if (KEEP) {
       const int i = L.inst;
@@ -268,9 +298,16 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
     }
     L.t = tnew;
     if (last) L.status = kSuccess;
-    L.err_prev = c.beta2 != 0.0
-                     ? ctl_pow(rmax(err, R(1e-4)), R(c.beta2))
-                     : R(1);
+    if constexpr (kSq)  // max(err, 1e-4)^beta2 = 2^(beta2/2 max(lg, log2 1e-8))
+      L.err_prev = c.beta2 != 0.0
+                       ? __builtin_amdgcn_exp2f(
+                             R(0.5 * c.beta2) *
+                             rmax(lg, R(-26.575424759098897)))
+                       : R(1);
+    else
+      L.err_prev = c.beta2 != 0.0
+                       ? ctl_pow(rmax(err, R(1e-4)), R(c.beta2))
+                       : R(1);
     L.n_acc += 1;
   }
   L.n_rej += accept ? 0 : 1;
@@ -307,6 +344,10 @@ __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
     if (a.st.status[inst] == kRunning) {
       load_lane(a, inst, L);
       f.load(a, inst, L.dim);
+      // Drain the lane's loads here (vmcnt 0; expcnt, lgkmcnt untouched):
+      // otherwise the step loop cannot tell them from the evaluation-time
+      // prefetch still in flight and waits for everything on every step.
+      __builtin_amdgcn_s_waitcnt(0x0F70);
       int used = 0;
       while (L.status == kRunning && used < a.budget) {
         attempt<R, M, F, REC, KEEP>(a, L, f);
@@ -421,6 +462,9 @@ __device__ __forceinline__ void init_one(const AnalyticArgs<R>& a, int i) {
                     L.dim);
     L.cursor += 1;
   }
+  for (int e = L.cursor; e < a.E; ++e)
+    for (int q = N; q < a.D; ++q)
+      a.y_eval[((long)i * a.E + e) * a.D + q] = R(0);
   L.h = R(0);
   if (L.te == L.t) {
     L.status = kSuccess;
