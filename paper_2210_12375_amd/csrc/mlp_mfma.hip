@@ -156,8 +156,7 @@ struct Bf3 {
   }
   // C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
   // B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit
-  // at Ah, Ah + plane, Ah + 2 plane.  The B fragments of block kb + 1 are
-  // in flight while block kb is multiplied.
+  // at Ah, Ah + plane, Ah + 2 plane.
   template <int MT, int NTW>
   __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
                                               const A* Ah, int plane, int lda,
@@ -165,19 +164,7 @@ struct Bf3 {
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    bf16x8 cur[NTW], nxt[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t)
-      if (t < ntiles)
-        cur[t] = gld8(Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8);
     for (int kb = 0; kb < nk; ++kb) {
-      if (kb + 1 < nk) {
-#pragma unroll
-        for (int t = 0; t < NTW; ++t)
-          if (t < ntiles)
-            nxt[t] = gld8(
-                Bp + ((size_t)((kb + 1) * nn + nb0 + t * nstep) * 64 + lane) * 8);
-      }
       bf16x8 ah[MT], am[MT], al[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -186,19 +173,24 @@ struct Bf3 {
         am[mt] = lds8(Ah + plane + off);
         al[mt] = lds8(Ah + 2 * plane + off);
       }
+      bf16x8 bfrag[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int nb = nb0 + t * nstep;
+        if (t < ntiles)
+          bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb) * 64 + lane) * 8);
+      }
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
         if (t < ntiles) {
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            acc[mt][t] = mfma(al[mt], cur[t], acc[mt][t]);
-            acc[mt][t] = mfma(am[mt], cur[t], acc[mt][t]);
-            acc[mt][t] = mfma(ah[mt], cur[t], acc[mt][t]);
+            acc[mt][t] = mfma(al[mt], bfrag[t], acc[mt][t]);
+            acc[mt][t] = mfma(am[mt], bfrag[t], acc[mt][t]);
+            acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
           }
         }
       }
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) cur[t] = nxt[t];
     }
   }
 };
@@ -220,33 +212,23 @@ struct F32 {
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    f32x4 c0[NTW], c1[NTW], n0[NTW], n1[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-      if (t < ntiles) {
-        const W* q = Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8;
-        c0[t] = *reinterpret_cast<const f32x4*>(q);
-        c1[t] = *reinterpret_cast<const f32x4*>(q + 4);
-      }
-    }
     for (int kb = 0; kb < nk; ++kb) {
-      if (kb + 1 < nk) {
-#pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-          if (t < ntiles) {
-            const W* q =
-                Bp + ((size_t)((kb + 1) * nn + nb0 + t * nstep) * 64 + lane) * 8;
-            n0[t] = *reinterpret_cast<const f32x4*>(q);
-            n1[t] = *reinterpret_cast<const f32x4*>(q + 4);
-          }
-        }
-      }
       f32x4 a0[MT], a1[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const A* p = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
         a0[mt] = *reinterpret_cast<const f32x4*>(p);
         a1[mt] = *reinterpret_cast<const f32x4*>(p + 4);
+      }
+      f32x4 b0[NTW], b1[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (t < ntiles) {
+          const W* q =
+              Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) * 8;
+          b0[t] = *reinterpret_cast<const f32x4*>(q);
+          b1[t] = *reinterpret_cast<const f32x4*>(q + 4);
+        }
       }
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
@@ -256,18 +238,13 @@ struct F32 {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  a0[mt][q], c0[t][q], acc[mt][t], 0, 0, 0);
+                  a0[mt][q], b0[t][q], acc[mt][t], 0, 0, 0);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  a1[mt][q], c1[t][q], acc[mt][t], 0, 0, 0);
+                  a1[mt][q], b1[t][q], acc[mt][t], 0, 0, 0);
           }
         }
-      }
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        c0[t] = n0[t];
-        c1[t] = n1[t];
       }
     }
   }
@@ -482,7 +459,8 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     any_running = 1;
   __syncthreads();
   if (!any_running) return;
-  const long K = a.K, kb = a.kb;
+  const long kb = a.kb;
+  const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
   auto on = [&](int row) { return row < B && a.act[row] == kRunning; };
 
   // prologue: Y_s and the probe into LDS, the layer-1 inputs into the tape
@@ -491,11 +469,11 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     const bool o = on(row);
     const float Yv = o ? a.Y[(long)row * D + c] : 0.f;
     Op::put(Xh, PX, r * SX + c, Yv);
-    if (row < B) a.T1in[(long)c * K + kb + row] = Yv;
+    if (row < B) a.T1in[(kb + row) * l1 + c] = Yv;
     if (CNF) {
       const float e = o ? a.eps[(long)row * D + c] : 0.f;
       Op::put(Xh, PX, (PR + r) * SX + c, e);
-      if (row < B) a.T1in[(long)c * K + kb + B + row] = e;
+      if (row < B) a.T1in[(kb + B + row) * l1 + c] = e;
     }
   }
   for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
@@ -508,11 +486,11 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
         on(row) ? float(a.bt[row] + a.c * double(a.bh[row])) : 0.f;
     tcol[r] = tv;
     if (row < B) {
-      a.T1in[(long)din * K + kb + row] = tv;
-      a.T1in[(long)(din + 1) * K + kb + row] = 1.f;
+      a.T1in[(kb + row) * l1 + din] = tv;
+      a.T1in[(kb + row) * l1 + din + 1] = 1.f;
       if (CNF) {
-        a.T1in[(long)din * K + kb + B + row] = 0.f;
-        a.T1in[(long)(din + 1) * K + kb + B + row] = 0.f;
+        a.T1in[(kb + B + row) * l1 + din] = 0.f;
+        a.T1in[(kb + B + row) * l1 + din + 1] = 0.f;
       }
     }
   }
@@ -565,7 +543,7 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
         keep[layer][t][i] = primal ? act : v;
         Op::put(Ah, PA, row * SA + n, act);
         const long k = tk(row);
-        if (k >= 0) Tin[(long)n * K + k] = act;
+        if (k >= 0) Tin[k * (H + 1) + n] = act;
       }
     }
     __syncthreads();
@@ -575,8 +553,8 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     const long k = tk(r);
     if (k < 0) continue;
     const float one = (!CNF || r < PR) ? 1.f : 0.f;
-    a.T2in[(long)H * K + k] = one;
-    a.T3in[(long)H * K + k] = one;
+    a.T2in[k * (H + 1) + H] = one;
+    a.T3in[k * (H + 1) + H] = one;
   }
 
   // gbar: kappa_z on primal rows, -kappa_l eps on tangent rows
@@ -585,13 +563,13 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     const bool o = on(row);
     const float kz = o ? a.kap_s[(long)row * D + c] : 0.f;
     Op::put(Xh, PX, r * SX + c, kz);
-    if (row < B) a.T3g[(long)c * K + kb + row] = kz;
+    if (row < B) a.T3g[(kb + row) * din + c] = kz;
     if (CNF) {
       const float g = o ? -a.kap_s[(long)row * D + din] *
                               a.eps[(long)row * D + c]
                         : 0.f;
       Op::put(Xh, PX, (PR + r) * SX + c, g);
-      if (row < B) a.T3g[(long)c * K + kb + B + row] = g;
+      if (row < B) a.T3g[(kb + B + row) * din + c] = g;
     }
   }
   __syncthreads();
@@ -630,7 +608,7 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
         }
         Op::put(Ah, PA, row * SA + n, g);
         const long k = tk(row);
-        if (k >= 0) Tg[(long)n * K + k] = g;
+        if (k >= 0) Tg[k * H + n] = g;
       }
     }
     __syncthreads();

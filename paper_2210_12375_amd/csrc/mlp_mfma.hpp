@@ -71,7 +71,7 @@ struct MfmaVjpArgs {
   const double* bt;    // [B] t_n
   double c;            // c_s
   MfmaWeights w;
-  // tape, feature-major [feature][K]; this stage's columns start at kb
+  // tape, sample-major [K][feature]; this stage's rows start at kb
   float *T1in, *T1g, *T2in, *T2g, *T3in, *T3g;
   long K, kb;
   int s, n;

@@ -103,17 +103,18 @@ struct Back {
   R* yseg;         // [k + 1, B, D] states of the current segment
   R* slots;        // [G, P] split-K partials of the parameter gradient
   int32_t* flags;  // [0]: max accepted steps, [1]: record overflow
-  // Tape of one step, feature-major ([feature][k], k = stage * Bs + row,
+  // Tape of one step, sample-major ([k][feature], k = stage * Bs + row,
   // Bs = B, or 2B for the CNF whose tangent rows follow the primal ones):
   // layer inputs with a trailing constant feature (1 on primal rows, 0 on
-  // tangent rows: the bias gradient) and the layer-output cotangents.
+  // tangent rows: the bias gradient) and the layer-output cotangents.  Row
+  // widths: T1in din + 2, T2in and T3in H + 1, T1g and T2g H, T3g din.
   R *T1in, *T1g, *T2in, *T2g, *T3in, *T3g;
   long K;  // 7 * Bs
   int32_t cap, k, G;
   long P;
 };
 
-constexpr int kSlots = 64;  // most k-splits of a parameter-gradient GEMM
+constexpr int kSlots = 128;  // most k-splits of a parameter-gradient GEMM
 
 inline long n_params(int din, int H) {
   const long n0 = din + 1;
@@ -1188,41 +1189,41 @@ __global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
     }
     // tape of this stage: layer inputs (+ bias feature) and cotangents
     {
-      const long Kt = b.K, Bs = cnf ? 2L * B : (long)B;
+      const long Bs = cnf ? 2L * B : (long)B;
       const long kb = (long)(s - 1) * Bs;
-      for (int idx = threadIdx.x; idx < ROWS * (n0 + 1); idx += blockDim.x) {
-        const int r = idx % ROWS, f = idx / ROWS, row = r0 + r;
+      const int l1 = n0 + 1, lh = H + 1;
+      for (int idx = threadIdx.x; idx < ROWS * l1; idx += blockDim.x) {
+        const int r = idx / l1, f = idx % l1, row = r0 + r;
         if (row >= B) continue;
-        b.T1in[(long)f * Kt + kb + row] = f < n0 ? X[r * n0 + f] : R(1);
-        if (cnf)
-          b.T1in[(long)f * Kt + kb + B + row] =
-              f < din ? dX[r * n0 + f] : R(0);
+        const long k = kb + row;
+        b.T1in[k * l1 + f] = f < n0 ? X[r * n0 + f] : R(1);
+        if (cnf) b.T1in[(k + B) * l1 + f] = f < din ? dX[r * n0 + f] : R(0);
       }
-      for (int idx = threadIdx.x; idx < ROWS * (H + 1); idx += blockDim.x) {
-        const int r = idx % ROWS, f = idx / ROWS, row = r0 + r;
+      for (int idx = threadIdx.x; idx < ROWS * lh; idx += blockDim.x) {
+        const int r = idx / lh, f = idx % lh, row = r0 + r;
         if (row >= B) continue;
-        const long o = (long)f * Kt + kb + row;
-        b.T2in[o] = f < H ? A1[r * H + f] : R(1);
-        b.T3in[o] = f < H ? A2[r * H + f] : R(1);
+        const long k = kb + row;
+        b.T2in[k * lh + f] = f < H ? A1[r * H + f] : R(1);
+        b.T3in[k * lh + f] = f < H ? A2[r * H + f] : R(1);
         if (f < H) {
-          b.T1g[o] = G1[r * H + f];
-          b.T2g[o] = G2[r * H + f];
+          b.T1g[k * H + f] = G1[r * H + f];
+          b.T2g[k * H + f] = G2[r * H + f];
         }
         if (cnf) {
-          b.T2in[o + B] = f < H ? DA1[r * H + f] : R(0);
-          b.T3in[o + B] = f < H ? DA2[r * H + f] : R(0);
+          b.T2in[(k + B) * lh + f] = f < H ? DA1[r * H + f] : R(0);
+          b.T3in[(k + B) * lh + f] = f < H ? DA2[r * H + f] : R(0);
           if (f < H) {
-            b.T1g[o + B] = DG1[r * H + f];
-            b.T2g[o + B] = DG2[r * H + f];
+            b.T1g[(k + B) * H + f] = DG1[r * H + f];
+            b.T2g[(k + B) * H + f] = DG2[r * H + f];
           }
         }
       }
       for (int idx = threadIdx.x; idx < ROWS * din; idx += blockDim.x) {
-        const int r = idx % ROWS, f = idx / ROWS, row = r0 + r;
+        const int r = idx / din, f = idx % din, row = r0 + r;
         if (row >= B) continue;
-        const long o = (long)f * Kt + kb + row;
-        b.T3g[o] = Kp[r * D + f];
-        if (cnf) b.T3g[o + B] = -Kp[r * D + din] * dX[r * n0 + f];
+        const long k = kb + row;
+        b.T3g[k * din + f] = Kp[r * D + f];
+        if (cnf) b.T3g[(k + B) * din + f] = -Kp[r * D + din] * dX[r * n0 + f];
       }
     }
     __syncthreads();
@@ -1337,9 +1338,10 @@ __global__ void copy_r(R* dst, const R* src, long n) {
 }
 
 // Parameter gradient of one step from its tape: for each layer,
-// C[m][n] += sum_k Tin[m][k] Tg[n][k] over the k range of this split, added
+// C[m][n] += sum_k Tin[k][m] Tg[k][n] over the k range of this split, added
 // into slot[split] (one owner per entry, so the sum is deterministic).  The
-// augmented C = [W; b] of the three layers, concatenated, is dtheta.
+// augmented C = [W; b] of the three layers, concatenated, is dtheta.  Tape
+// rows are M (inputs) and N (cotangents) wide.
 template <typename R>
 __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
                                                  long K, int M, int N, int S,
@@ -1359,13 +1361,12 @@ __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = R(0);
   for (long kk = k0; kk < k1; kk += TK) {
-    // load TK x 64 of each operand (row m of Tin is contiguous in k)
     for (int e = threadIdx.x; e < TK * TM; e += 256) {
-      const int kl = e % TK, ml = e / TK;
+      const int kl = e / TM, c = e % TM;
       const long k = kk + kl;
-      const int m = m0 + ml, n = n0 + ml;
-      As[kl][ml] = (m < M && k < k1) ? Tin[(long)m * K + k] : R(0);
-      Bs[kl][ml] = (n < N && k < k1) ? Tg[(long)n * K + k] : R(0);
+      const int m = m0 + c, n = n0 + c;
+      As[kl][c] = (m < M && k < k1) ? Tin[k * M + m] : R(0);
+      Bs[kl][c] = (n < N && k < k1) ? Tg[k * N + n] : R(0);
     }
     __syncthreads();
 #pragma unroll
@@ -1394,53 +1395,81 @@ __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
 }
 
 // FP32 tapes: the same product on the FP32 matrix cores
-// (v_mfma_f32_16x16x4_f32: exact FP32 products, FP32 accumulation).  A
-// 128 x 128 tile of C per workgroup, 64 x 64 per wavefront (4 x 4 MFMA
-// tiles); both operands staged through LDS 16 k-columns at a time (tape
-// rows are contiguous in k).
+// (v_mfma_f32_16x16x4_f32: exact FP32 products, FP32 accumulation).  Four
+// wavefronts in a 2 x 2 grid, each WM x WN 16x16 tiles, so a workgroup
+// covers (32 WM) x (32 WN) of C: 128 x 128 for the square layers, 32 x 128
+// or 128 x 32 where the layer has few inputs or outputs.  Both operands
+// pass through LDS 16 tape rows at a time (contiguous runs of features).
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+template <int WM, int WN>
 __global__ __launch_bounds__(256) void grad_gemm_mfma(
     const float* Tin, const float* Tg, long K, int M, int N, int S,
     float* slots, long P, long off) {
-  constexpr int TT = 128, TK = 16, LD = TK + 1;
-  __shared__ float As[TT * LD];
-  __shared__ float Bs[TT * LD];
-  const int tiles_n = (N + TT - 1) / TT;
+  constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16;
+  // row pitch 16 floats past the tile: the four lane groups of an operand
+  // read land 16 banks apart
+  constexpr int LA = TM + 16, LB = TN + 16;
+  constexpr int NA = TK * TM / 256, NB = TK * TN / 256;  // loads per thread
+  __shared__ float As[TK * LA];
+  __shared__ float Bs[TK * LB];
+  const int tiles_n = (N + TN - 1) / TN;
   const int tile = blockIdx.x / S, split = blockIdx.x % S;
-  const int m0 = (tile / tiles_n) * TT, n0 = (tile % tiles_n) * TT;
+  const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
   const long kc = ((K + S - 1) / S + TK - 1) / TK * TK;
   const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
   const int lr = lane & 15, lk = lane >> 4;
-  f32x4_t acc[4][4];
+  f32x4_t acc[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // the next 16 tape rows are loaded into registers while the current ones
+  // are multiplied
+  float ra[NA], rb[NB];
+  auto fetch = [&](long kk) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q, kl = e / TM, c = e % TM;
+      const long k = kk + kl;
+      const int m = m0 + c;
+      ra[q] = (m < M && k < k1) ? Tin[k * M + m] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q, kl = e / TN, c = e % TN;
+      const long k = kk + kl;
+      const int n = n0 + c;
+      rb[q] = (n < N && k < k1) ? Tg[k * N + n] : 0.f;
+    }
+  };
+  if (k0 < k1) fetch(k0);
   for (long kk = k0; kk < k1; kk += TK) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q, row = e / TK, kl = e % TK;
-      const long k = kk + kl;
-      const int m = m0 + row, n = n0 + row;
-      As[row * LD + kl] = (m < M && k < k1) ? Tin[(long)m * K + k] : 0.f;
-      Bs[row * LD + kl] = (n < N && k < k1) ? Tg[(long)n * K + k] : 0.f;
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      As[(e / TM) * LA + e % TM] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      Bs[(e / TN) * LB + e % TN] = rb[q];
     }
     __syncthreads();
+    if (kk + TK < k1) fetch(kk + TK);
 #pragma unroll
     for (int k4 = 0; k4 < TK; k4 += 4) {
-      float a[4], b[4];
+      float a[WM], b[WN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[(wm + i * 16 + lr) * LD + k4 + lk];
-        b[i] = Bs[(wn + i * 16 + lr) * LD + k4 + lk];
-      }
+      for (int i = 0; i < WM; ++i) a[i] = As[(k4 + lk) * LA + wm + i * 16 + lr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < WN; ++j) b[j] = Bs[(k4 + lk) * LB + wn + j * 16 + lr];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
           acc[i][j] =
               __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
@@ -1448,9 +1477,9 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
   }
   float* slot = slots + (long)split * P + off;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm + i * 16 + lk * 4 + v;
@@ -1462,20 +1491,33 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int S, R* slots, long P, long off, hipStream_t s) {
-  // k-splits: enough workgroups for the chip (about 1024), each split at
-  // least 256 columns of the tape long, at most the S slots there are
-  const int tt = std::is_same<R, float>::value ? 128 : 64;
-  const int tiles = ((M + tt - 1) / tt) * ((N + tt - 1) / tt);
-  int splits = (1024 + tiles - 1) / tiles;
+  // tile shape: narrow where the layer has few inputs or outputs
+  const bool f32 = std::is_same<R, float>::value;
+  const int tm = !f32 ? 64 : (M <= 32 ? 32 : 128);
+  const int tn = !f32 ? 64 : (N <= 32 && M > 32 ? 32 : 128);
+  const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
+  // k-splits: a few rounds of workgroups over the chip (about 2048, so the
+  // last round's tail is short), each split at least 256 tape rows long, at
+  // most the S slots there are
+  int splits = (2048 + tiles - 1) / tiles;
   const long by_k = K / 256 > 0 ? K / 256 : 1;
   if (splits > by_k) splits = (int)by_k;
   if (splits > S) splits = S;
-  if constexpr (std::is_same<R, float>::value)
-    hipLaunchKernelGGL(grad_gemm_mfma, dim3(tiles * splits), dim3(256), 0, s,
-                       Tin, Tg, K, M, N, splits, slots, P, off);
-  else
-    hipLaunchKernelGGL(grad_gemm<R>, dim3(tiles * splits), dim3(256), 0, s,
-                       Tin, Tg, K, M, N, splits, slots, P, off);
+  const dim3 g(tiles * splits), blk(256);
+  if constexpr (std::is_same<R, float>::value) {
+    if (tm == 32)
+      hipLaunchKernelGGL((grad_gemm_mfma<1, 4>), g, blk, 0, s, Tin, Tg, K, M,
+                         N, splits, slots, P, off);
+    else if (tn == 32)
+      hipLaunchKernelGGL((grad_gemm_mfma<4, 1>), g, blk, 0, s, Tin, Tg, K, M,
+                         N, splits, slots, P, off);
+    else
+      hipLaunchKernelGGL((grad_gemm_mfma<4, 4>), g, blk, 0, s, Tin, Tg, K, M,
+                         N, splits, slots, P, off);
+  } else {
+    hipLaunchKernelGGL(grad_gemm<R>, g, blk, 0, s, Tin, Tg, K, M, N, splits,
+                       slots, P, off);
+  }
   return hipGetLastError();
 }
 
