@@ -1,0 +1,387 @@
+// Device building blocks of the neural-field kernels on the matrix cores of
+// gfx950, shared by the per-stage field kernel, the adjoint-stage kernel
+// and the fused persistent solver.
+//
+// Two operand policies: BF16 mode (Bf3) issues v_mfma_f32_16x16x32_bf16
+// with BF16 weights and activations split into three BF16 terms hi + mid +
+// lo (24 significant bits, FP32's precision, so activation rounding does not
+// masquerade as local error at tolerances near 1e-5); FP32 mode (F32) issues
+// v_mfma_f32_16x16x4_f32 with FP32 weights and activations (each 32-wide k
+// block is eight 4-wide products over the same lane layout, so packing and
+// LDS addressing are shared).  Weights are packed once per solve into 16x32
+// B-fragments (64 lanes x 8 elements contiguous per fragment), read straight
+// from L2 by each wavefront.  Accumulation is FP32; biases, the time input
+// (a rank-1 term t * W1[t, :]) and tanh are applied in the epilogue, whose
+// output goes back to LDS for the next layer.
+//
+// For the CNF field the tangent rows (the Jacobian-vector product with the
+// Rademacher probe) are stacked under the primal rows of the same 16-row
+// MFMA tile (8 + 8): the tangent epilogue takes tanh' from the partner lane
+// (lane ^ 32 holds the same column of the primal row 8 above).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "mlp_mfma.hpp"
+
+namespace bode {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace mtile {
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u)  // inf / nan stay inf / nan
+    return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) {
+  return __uint_as_float(uint32_t(h) << 16);
+}
+
+struct Dims {
+  int K1, nk1, nn1, nk2, nn2, nk3, nn3;
+  size_t off2, off3;  // packed offsets (elements) of layers 2 and 3
+};
+
+__host__ __device__ inline Dims dims(int din, int H) {
+  Dims d;
+  d.K1 = (din + 31) / 32 * 32;
+  d.nk1 = d.K1 / 32;
+  d.nn1 = H / 16;
+  d.nk2 = H / 32;
+  d.nn2 = H / 16;
+  d.nk3 = H / 32;
+  d.nn3 = din / 16;
+  d.off2 = (size_t)d.nk1 * d.nn1 * 512;
+  d.off3 = d.off2 + (size_t)d.nk2 * d.nn2 * 512;
+  return d;
+}
+
+// Packed layout: fragment f = kb * nn + nb, lane l, element i holds
+// M[kb*32 + (l/16)*8 + i][nb*16 + l%16] (zero beyond K rows), where M is a
+// layer W or its transpose.
+//
+// Transposed layers: W3^T [din x H], W2^T [H x H], W1^T [H x din].
+struct DimsT {
+  int nk3, nn3, nk2, nn2, nk1, nn1;
+  size_t off2, off1, total;
+};
+
+__host__ __device__ inline DimsT dims_t(int din, int H) {
+  DimsT d;
+  d.nk3 = (din + 31) / 32;
+  d.nn3 = H / 16;
+  d.nk2 = H / 32;
+  d.nn2 = H / 16;
+  d.nk1 = H / 32;
+  d.nn1 = din / 16;
+  d.off2 = (size_t)d.nk3 * d.nn3 * 512;
+  d.off1 = d.off2 + (size_t)d.nk2 * d.nn2 * 512;
+  d.total = d.off1 + (size_t)d.nk1 * d.nn1 * 512;
+  return d;
+}
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__device__ __forceinline__ bf16x8 gld8(const uint16_t* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// v = hi + mid + lo in bf16 (terms at Ah, Ah + plane, Ah + 2 plane).
+__device__ __forceinline__ void put_split(uint16_t* Ah, int plane, int off,
+                                          float v) {
+  const uint16_t h = f2bf(v);
+  const float r1 = v - bf2f(h);
+  const uint16_t m = f2bf(r1);
+  Ah[off] = h;
+  Ah[plane + off] = m;
+  Ah[2 * plane + off] = f2bf(r1 - bf2f(m));
+}
+
+struct Bf3 {
+  typedef uint16_t W;  // packed weight element
+  typedef uint16_t A;  // LDS activation element
+  static constexpr int kPlanes = 3, kPad = 8;
+  __device__ static __forceinline__ void put(A* p, int plane, int off,
+                                             float v) {
+    put_split(p, plane, off, v);
+  }
+  // C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
+  // B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit
+  // at Ah, Ah + plane, Ah + 2 plane.
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
+                                              const A* Ah, int plane, int lda,
+                                              const W* Bp, int nk, int nn,
+                                              int nb0, int nstep, int ntiles,
+                                              int lane) {
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    for (int kb = 0; kb < nk; ++kb) {
+      bf16x8 ah[MT], am[MT], al[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int off = (mt * 16 + r) * lda + kb * 32 + kq;
+        ah[mt] = lds8(Ah + off);
+        am[mt] = lds8(Ah + plane + off);
+        al[mt] = lds8(Ah + 2 * plane + off);
+      }
+      bf16x8 bfrag[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int nb = nb0 + t * nstep;
+        if (t < ntiles)
+          bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb) * 64 + lane) * 8);
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (t < ntiles) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][t] = mfma(al[mt], bfrag[t], acc[mt][t]);
+            acc[mt][t] = mfma(am[mt], bfrag[t], acc[mt][t]);
+            acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
+          }
+        }
+      }
+    }
+  }
+};
+
+// FP32 policy: A and B fragments are 8 FP32 values per lane; product q of
+// a 32-wide k block takes element q of both (the 4 k indices of one
+// 16x16x4 product are kb*32 + g*8 + q, g = lane / 16).
+struct F32 {
+  typedef float W;
+  typedef float A;
+  static constexpr int kPlanes = 1, kPad = 4;
+  __device__ static __forceinline__ void put(A* p, int, int off, float v) {
+    p[off] = v;
+  }
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
+                                              const A* Ah, int, int lda,
+                                              const W* Bp, int nk, int nn,
+                                              int nb0, int nstep, int ntiles,
+                                              int lane) {
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    for (int kb = 0; kb < nk; ++kb) {
+      f32x4 a0[MT], a1[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const A* p = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
+        a0[mt] = *reinterpret_cast<const f32x4*>(p);
+        a1[mt] = *reinterpret_cast<const f32x4*>(p + 4);
+      }
+      f32x4 b0[NTW], b1[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (t < ntiles) {
+          const W* q =
+              Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) * 8;
+          b0[t] = *reinterpret_cast<const f32x4*>(q);
+          b1[t] = *reinterpret_cast<const f32x4*>(q + 4);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (t < ntiles) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  a0[mt][q], b0[t][q], acc[mt][t], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  a1[mt][q], b1[t][q], acc[mt][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+};
+
+// The field for the 16-row tile starting at instance r0 (MLP: 16
+// instances; CNF: 8 instances and their 8 tangent rows), by a workgroup of
+// 4 wavefronts; NTW = H / 64 column tiles per wavefront in the hidden
+// layers.  smem_raw: mfma_smem<Op, NTW, CNF>(din) bytes of LDS.
+template <class Op, int NTW, bool CNF>
+__device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
+                                           unsigned char* smem_raw) {
+  constexpr int MT = 1;
+  typedef typename Op::A A;
+  typedef typename Op::W W;
+  constexpr int RT = 16 * MT;
+  constexpr int PR = CNF ? 8 : RT;  // instances per workgroup
+  constexpr int H = NTW * 64;
+  constexpr int SA = H + Op::kPad;  // LDS row stride (bank spread)
+  const int din = a.din, D = a.D, B = a.B;
+  const Dims dm = dims(din, H);
+  const int SX = dm.K1 + Op::kPad;
+  const int PX = RT * SX, PA = RT * SA;  // split-term planes
+  A* Xh = reinterpret_cast<A*>(smem_raw);
+  A* Ah = Xh + Op::kPlanes * PX;
+  float* tcol = reinterpret_cast<float*>(Ah + Op::kPlanes * PA);  // [PR]
+  float* red = tcol + PR;                                 // [PR][nn3]
+  __shared__ int any_running;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) any_running = 0;
+  __syncthreads();
+  if (tid < PR && r0 + tid < B && a.status[r0 + tid] == kRunning)
+    any_running = 1;
+  __syncthreads();
+  if (!any_running) return;
+
+  // prologue: stage input (FP32) -> split bf16 in LDS; tangent rows = probe
+  for (int idx = tid; idx < PR * D; idx += blockDim.x) {
+    const int r = idx / D, c = idx % D, row = r0 + r;
+    float Yv = 0.f;
+    if (row < B) {
+      float acc = 0.f;
+      for (int j = 0; j < a.n; ++j)
+        acc += a.coef[j] * a.K[((long)a.kidx[j] * B + row) * D + c];
+      Yv = a.y[(long)row * D + c] + a.hs[row] * acc;
+      if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
+    }
+    if (c < din) Op::put(Xh, PX, r * SX + c, Yv);
+  }
+  for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
+    const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
+    Op::put(Xh, PX, r * SX + c, 0.f);
+  }
+  if (CNF) {
+    for (int idx = tid; idx < PR * din; idx += blockDim.x) {
+      const int r = idx / din, c = idx % din, row = r0 + r;
+      const float e = row < B ? a.eps[(long)row * D + c] : 0.f;
+      Op::put(Xh, PX, (PR + r) * SX + c, e);
+    }
+  }
+  for (int r = tid; r < PR; r += blockDim.x) {
+    const int row = r0 + r;
+    tcol[r] = row < B ? float(a.t[row] + a.c * double(a.hs[row])) : 0.f;
+  }
+  __syncthreads();
+
+  const float* b1 = a.w.fvec;
+  const float* w1t = b1 + H;
+  const float* b2 = b1 + 2 * H;
+  const float* b3 = b1 + 3 * H;
+  const int rq = (lane >> 4) * 4, col = lane & 15;
+
+  // hidden layers: wave w owns column tiles w * NTW .. w * NTW + NTW - 1
+  for (int layer = 0; layer < 2; ++layer) {
+    f32x4 acc[MT][NTW];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (layer == 0)
+      Op::template gemm<MT, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
+                    NTW, lane);
+    else
+      Op::template gemm<MT, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
+                    wave * NTW, 1, NTW, lane);
+    __syncthreads();  // every wave has read its layer input
+    const float* bias = layer == 0 ? b1 : b2;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = mt * 16 + rq + i;
+          float v = acc[mt][t][i];
+          const bool primal = !CNF || row < PR;
+          if (primal) {
+            v += bias[n];
+            if (layer == 0) v += tcol[row] * w1t[n];
+          }
+          float act = primal ? tanhf(v) : 0.f;
+          if (CNF) {
+            const float ap = __shfl_xor(act, 32, 64);  // primal of row - 8
+            if (!primal) act = (1.f - ap * ap) * v;
+          }
+          Op::put(Ah, PA, row * SA + n, act);
+        }
+      }
+    __syncthreads();
+  }
+
+  // output layer: column tiles nb = wave, wave + 4, ...
+  {
+    const int ntiles = (dm.nn3 - wave + 3) / 4;
+    f32x4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (ntiles > 0)
+      Op::template gemm<MT, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off3, dm.nk3, dm.nn3, wave,
+                  4, ntiles, lane);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= ntiles) continue;
+        const int nb = wave + 4 * t;
+        const int n = nb * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = mt * 16 + rq + i;
+          const float v = acc[mt][t][i];
+          if (!CNF || r < PR) {
+            const int row = r0 + r;
+            if (row < B) a.out[(long)row * D + n] = v + b3[n];
+          } else {
+            // tangent row: eps_n * (dg/dz eps)_n, summed over the 16 columns
+            const int pr = r - PR, row = r0 + pr;
+            float q = row < B ? a.eps[(long)row * D + n] * v : 0.f;
+            q += __shfl_xor(q, 1, 64);
+            q += __shfl_xor(q, 2, 64);
+            q += __shfl_xor(q, 4, 64);
+            q += __shfl_xor(q, 8, 64);
+            if (col == 0) red[pr * dm.nn3 + nb] = q;
+          }
+        }
+      }
+    if (CNF) {
+      __syncthreads();
+      for (int pr = tid; pr < PR; pr += blockDim.x) {
+        const int row = r0 + pr;
+        float q = 0.f;
+        for (int nb = 0; nb < dm.nn3; ++nb) q += red[pr * dm.nn3 + nb];
+        if (row < B) a.out[(long)row * D + din] = -q;
+      }
+    }
+  }
+}
+
+template <class Op, int NTW, bool CNF>
+__host__ __device__ inline size_t mfma_smem(int din) {
+  constexpr int MT = 1;
+  constexpr int RT = 16 * MT, PR = CNF ? 8 : RT, H = NTW * 64;
+  const Dims dm = dims(din, H);
+  return sizeof(typename Op::A) * Op::kPlanes *
+             ((size_t)RT * (dm.K1 + Op::kPad) + RT * (H + Op::kPad)) +
+         sizeof(float) * (PR + PR * dm.nn3);
+}
+
+}  // namespace mtile
+}  // namespace bode

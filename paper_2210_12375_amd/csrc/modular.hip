@@ -27,6 +27,7 @@
 #include "common.hpp"
 #include "modular.hpp"
 #include "mlp_mfma.hpp"
+#include "mlp_mfma_tile.hpp"
 #include "tableau.hpp"
 
 namespace bode {
@@ -454,9 +455,7 @@ __global__ void mod_start_b(Mod<R> m, int probe) {
 
 // Error norm, controller, accept / reject, dense output, commit.
 template <typename R, class M, bool KEEP>
-__global__ __launch_bounds__(256) void commit_kernel(Mod<R> m) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+__device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
   if (row >= m.B || m.st.status[row] != kRunning) return;
   const int D = m.D, B = m.B;
   const R hs = m.hs[row];
@@ -574,6 +573,83 @@ __global__ __launch_bounds__(256) void commit_kernel(Mod<R> m) {
     }
   }
   if (status != kRunning) finish_row(m, row, lane, status, cursor);
+}
+
+template <typename R, class M, bool KEEP>
+__global__ __launch_bounds__(256) void commit_kernel(Mod<R> m) {
+  commit_row<R, M, KEEP>(m, blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6),
+                         threadIdx.x & 63);
+}
+
+// ---- fused persistent solve (matrix-core fields) ------------------------------
+//
+// One launch per solve: a workgroup owns one 16-row tile of the field kernel
+// (16 instances, or 8 CNF instances with their tangent rows) and runs its
+// instances' attempts to the end: the six new stage evaluations of an
+// attempt, then each row's commit by one wavefront.  Instances are
+// independent (each has its own step, section 3), so no workgroup waits on
+// another and there is no per-round launch or host round trip.  Stage
+// outputs pass between the waves of the tile through memory; the barrier
+// between stages orders them (all waves share the compute unit's cache).
+struct FusedArgs {
+  MfmaArgs st[6];  // stages 2..7: combination, node, output
+  int budget;      // attempts per instance
+};
+
+template <class Op, int NTW, bool CNF, class M>
+__global__ __launch_bounds__(256) void solve_fused_kernel(Mod<float> m,
+                                                          FusedArgs f) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int PR = CNF ? 8 : 16;
+  const int r0 = blockIdx.x * PR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ int active;
+  for (int round = 0; round < f.budget; ++round) {
+    __syncthreads();
+    if (threadIdx.x == 0) active = 0;
+    __syncthreads();
+    if (threadIdx.x < PR && r0 + (int)threadIdx.x < m.B &&
+        m.st.status[r0 + threadIdx.x] == kRunning)
+      active = 1;
+    __syncthreads();
+    if (!active) break;
+    for (int s = 0; s < 6; ++s) {
+      mtile::field_tile<Op, NTW, CNF>(f.st[s], r0, smem_raw);
+      __syncthreads();
+    }
+    for (int r = wave; r < PR; r += 4)
+      commit_row<float, M, false>(m, r0 + r, lane);
+  }
+}
+
+template <class Op, int NTW, bool CNF, class M>
+hipError_t fused_t(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
+  constexpr int PR = CNF ? 8 : 16;
+  const size_t sm = mtile::mfma_smem<Op, NTW, CNF>(m.d_in);
+  if (sm > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((solve_fused_kernel<Op, NTW, CNF, M>),
+                     dim3((m.B + PR - 1) / PR), dim3(256), sm, s, m, f);
+  return hipGetLastError();
+}
+
+template <class Op, bool CNF, class M>
+hipError_t fused_h(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
+  switch (m.H) {
+    case 512: return fused_t<Op, 8, CNF, M>(m, f, s);
+    case 256: return fused_t<Op, 4, CNF, M>(m, f, s);
+    case 128: return fused_t<Op, 2, CNF, M>(m, f, s);
+    default: return fused_t<Op, 1, CNF, M>(m, f, s);
+  }
+}
+
+template <class M>
+hipError_t fused_launch(const Mod<float>& m, const FusedArgs& f, int f32,
+                        hipStream_t s) {
+  if (f32)
+    return m.cnf ? fused_h<mtile::F32, true, M>(m, f, s)
+                 : fused_h<mtile::F32, false, M>(m, f, s);
+  return m.cnf ? fused_h<mtile::Bf3, true, M>(m, f, s)
+               : fused_h<mtile::Bf3, false, M>(m, f, s);
 }
 
 __global__ void count_equal_kernel(const int32_t* a, int n, int32_t v,
@@ -766,24 +842,44 @@ hipError_t field<double>(ModImpl&, const Mod<double>& m, const StageSpec& sp,
   return launch_field_fma<double>(m, sp, out, s);
 }
 
+MfmaArgs stage_args(const ModImpl& im, const Mod<float>& m,
+                    const StageSpec& sp, float* out) {
+  MfmaArgs a = mfma_args(m.B, m.D, m.d_in, m.H, m.cnf, m.st.status, m.st.y,
+                         m.K, m.Y7, m.hs, m.st.t, m.eps, im.mw);
+  a.n = sp.n;
+  for (int j = 0; j < 6; ++j) {
+    a.kidx[j] = sp.kidx[j];
+    a.coef[j] = float(sp.coef[j]);
+  }
+  a.c = sp.c;
+  a.write_y7 = sp.yout != nullptr;
+  a.Y7 = static_cast<float*>(sp.yout);
+  a.out = out;
+  return a;
+}
+
 template <>
 hipError_t field<float>(ModImpl& im, const Mod<float>& m, const StageSpec& sp,
                         float* out, hipStream_t s) {
-  if (im.mw.packed != nullptr) {
-    MfmaArgs a = mfma_args(m.B, m.D, m.d_in, m.H, m.cnf, m.st.status, m.st.y,
-                           m.K, m.Y7, m.hs, m.st.t, m.eps, im.mw);
-    a.n = sp.n;
-    for (int j = 0; j < 6; ++j) {
-      a.kidx[j] = sp.kidx[j];
-      a.coef[j] = float(sp.coef[j]);
-    }
-    a.c = sp.c;
-    a.write_y7 = sp.yout != nullptr;
-    a.Y7 = static_cast<float*>(sp.yout);
-    a.out = out;
-    return launch_field_mfma(a, get_row_tile(im.cfg), s);
-  }
+  if (im.mw.packed != nullptr)
+    return launch_field_mfma(stage_args(im, m, sp, out), get_row_tile(im.cfg),
+                             s);
   return launch_field_fma<float>(m, sp, out, s);
+}
+
+// The whole solve (up to budget attempts per instance) in one launch of the
+// fused kernel.
+template <class M>
+hipError_t run_fused(const ModImpl& im, const Mod<float>& m, int budget,
+                     hipStream_t s) {
+  FusedArgs f{};
+  for (int st = 1; st < 7; ++st) {
+    StageSpec sp = stage_spec<M>(st);
+    if (st == 6) sp.yout = m.Y7;
+    f.st[st - 1] = stage_args(im, m, sp, m.K + (size_t)st * m.B * m.D);
+  }
+  f.budget = budget;
+  return fused_launch<M>(m, f, im.mw.f32, s);
 }
 
 template <typename R>
@@ -837,6 +933,11 @@ hipError_t init_launch(ModImpl& im, Mod<R>& m, hipStream_t s) {
 
 template <typename R>
 hipError_t run_rounds(ModImpl& im, Mod<R>& m, int budget, hipStream_t s) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (im.mw.packed != nullptr && !m.keep)
+      return im.cfg.method == BODE_TSIT5 ? run_fused<Tsit5>(im, m, budget, s)
+                                         : run_fused<Dopri5>(im, m, budget, s);
+  }
   int done = 0;
   while (done < budget) {
     const int chunk = budget - done < kRoundsPerSync ? budget - done
@@ -917,6 +1018,7 @@ hipError_t modular_init(ModularPlan& mp, const bode_config& c,
     mp.cursor = m.st.cursor;
     mp.prev_rej = m.st.prev_rej;
     mp.h_rec = m.h_rec;
+    mp.n_running = m.n_running;
   };
   if (im->is64) {
     fill_mod<double>(&im->md, c, p);

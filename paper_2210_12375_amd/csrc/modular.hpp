@@ -23,7 +23,8 @@ struct ModularPlan {
           *n_fe = nullptr, *status = nullptr, *cursor = nullptr,
           *prev_rej = nullptr;
   double* h_rec = nullptr;
-  void* impl = nullptr;  // kernel-side plan (owned)
+  int32_t* n_running = nullptr;  // device counter (1 int) in the workspace
+  void* impl = nullptr;          // kernel-side plan (owned)
 };
 
 size_t modular_layout(const bode_config& c, void* base, ModularPlan* mp);

@@ -358,6 +358,7 @@ int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
         solver_destroy(s);
         return fail(nullptr, BODE_EHIP, m);
       }
+      s->n_running_dev = s->mp.n_running;
     }
     *out = s;
     return BODE_OK;
@@ -378,6 +379,8 @@ int solver_step(bode_solver* s, int32_t n_attempts, int32_t* n_running_host) {
     if (rc != BODE_OK) return rc;
     s->stepped = true;
     if (n_running_host) {
+      if (s->n_running_dev == nullptr)
+        return fail(s, BODE_ESTATE, "no running-count buffer in this plan");
       HIP_TRY(bode::launch_fill_i32(s->n_running_dev, 1, 0, s->stream));
       HIP_TRY(bode::launch_count_equal(status_ptr(s), s->cfg.B, bode::kRunning,
                                        s->n_running_dev, s->stream));

@@ -159,3 +159,49 @@ def test_field_kernel_shapes(precision, d, hidden, cnf):
     tol = TOL_FP32 if precision == "fp32" else TOL_BF16
     flush(f"  max rel {rel.max():.2e}")
     assert rel.max() <= tol, (rel.max(), np.argmax(rel))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fused_solve_slices_and_edges(precision):
+    """The matrix-core modes run a whole solve in one persistent launch:
+    solver_step in slices of 3 attempts equals one solver_solve bitwise (and
+    reports a falling running count); a step limit, an instance with t_end =
+    t0 and an invalid one end with their statuses; a keep_dense solve (the
+    per-stage path) agrees with the fused one."""
+    flush(f"fused solve {precision}")
+    p = W.neural_ode_fit(B=53)
+    p["t_end"][3] = 0.0
+    p["t_eval"][3] = 0.0
+    p["atol"][7] = -1.0
+    g, _ = run_gpu(p, precision=precision, rhs=bd.RHS_MLP, record_cap=256)
+    assert g["status"][3] == bd.SUCCESS and g["status"][7] == bd.INVALID
+    ok = np.flatnonzero(g["status"] != bd.INVALID)
+    assert np.all(g["status"][ok] == bd.SUCCESS)
+    dp = bd.device_problem(p, precision)
+    s = bd.Solver(dp, precision=precision, rhs=bd.RHS_MLP, record_cap=256)
+    running = []
+    for _ in range(1000):
+        n = s.step(3, want_running=True)
+        running.append(n)
+        if n == 0:
+            break
+    assert running[-1] == 0 and running[0] > 0
+    assert all(a >= b for a, b in zip(running, running[1:]))
+    np.testing.assert_array_equal(s.y_final.double().cpu().numpy(),
+                                  g["y_final"])
+    np.testing.assert_array_equal(s.y_eval.double().cpu().numpy(),
+                                  g["y_eval"])
+    st = s.stats()
+    np.testing.assert_array_equal(st["n_attempted"].cpu().numpy(),
+                                  g["n_attempted"])
+    s.close()
+    # step limit
+    lim, _ = run_gpu(p, precision=precision, rhs=bd.RHS_MLP, max_steps=3)
+    assert np.all(lim["n_attempted"][ok] <= 3)
+    hit = g["n_attempted"][ok] > 3
+    assert np.all(lim["status"][ok][hit] == bd.MAX_STEPS)
+    # the per-stage path (kept interpolant) takes the same steps
+    k, _ = run_gpu(p, precision=precision, rhs=bd.RHS_MLP, keep_dense=1)
+    np.testing.assert_array_equal(k["n_attempted"], g["n_attempted"])
+    np.testing.assert_allclose(k["y_final"][ok], g["y_final"][ok], rtol=0,
+                               atol=1e-5 * np.abs(g["y_final"][ok]).max())
