@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
           v += bias[n];
           if (layer == 0) v += tcol[row] * w1t[n];
         }
-        float act = primal ? tanhf(v) : 0.f;
+        float act = primal ? fast_tanh(v) : 0.f;
         if (CNF) {
           const float ap = __shfl_xor(act, 32, 64);
           if (!primal) act = (1.f - ap * ap) * v;

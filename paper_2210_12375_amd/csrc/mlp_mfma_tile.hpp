@@ -42,9 +42,6 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
   return uint16_t(u >> 16);
 }
 
-__device__ __forceinline__ float bf2f(uint16_t h) {
-  return __uint_as_float(uint32_t(h) << 16);
-}
 
 struct Dims {
   int K1, nk1, nn1, nk2, nn2, nk3, nn3;
@@ -101,15 +98,28 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// v = hi + mid + lo in bf16 (terms at Ah, Ah + plane, Ah + 2 plane).
+// v = hi + mid + lo in bf16 (terms at Ah, Ah + plane, Ah + 2 plane), by
+// truncation: hi keeps v's top 16 bits (8 significant), the residual v - hi
+// is exact with at most 16 significant bits, mid keeps its top 8, and the
+// last residual has at most 8, so it is a bf16 value: the sum is v exactly.
 __device__ __forceinline__ void put_split(uint16_t* Ah, int plane, int off,
                                           float v) {
-  const uint16_t h = f2bf(v);
-  const float r1 = v - bf2f(h);
-  const uint16_t m = f2bf(r1);
-  Ah[off] = h;
-  Ah[plane + off] = m;
-  Ah[2 * plane + off] = f2bf(r1 - bf2f(m));
+  const uint32_t u = __float_as_uint(v);
+  const float r1 = v - __uint_as_float(u & 0xffff0000u);
+  const uint32_t u1 = __float_as_uint(r1);
+  const float r2 = r1 - __uint_as_float(u1 & 0xffff0000u);
+  Ah[off] = uint16_t(u >> 16);
+  Ah[plane + off] = uint16_t(u1 >> 16);
+  Ah[2 * plane + off] = uint16_t(__float_as_uint(r2) >> 16);
+}
+
+// tanh x = 1 - 2 / (1 + e^{2x}), e^{2x} = 2^(2 x log2 e) by the hardware
+// exp2 and reciprocal: absolute error about 1e-7 (FP32's own rounding of an
+// activation), and the limits come out exactly (e^{2x} = inf gives 1, 0
+// gives -1).
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
 }
 
 struct Bf3 {
@@ -313,7 +323,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
             v += bias[n];
             if (layer == 0) v += tcol[row] * w1t[n];
           }
-          float act = primal ? tanhf(v) : 0.f;
+          float act = primal ? fast_tanh(v) : 0.f;
           if (CNF) {
             const float ap = __shfl_xor(act, 32, 64);  // primal of row - 8
             if (!primal) act = (1.f - ap * ap) * v;
