@@ -250,6 +250,36 @@ def neural_suite(bd, W, rl, steps, warmup):
     return out
 
 
+def pid_study(bd, W):
+    """Appendix C's controller study: accepted + rejected steps for one Van
+    der Pol cycle per mu, integral controller against PI and PID laws on
+    log err (Gustafsson's PI; Soderlind's H211PI and H312PID filters; a PID
+    with gains 0.3, 0.4, 0.1), FP64 Dormand-Prince on the GPU."""
+    import torch
+    p = W.vdp_cycles()
+    dp = bd.device_problem(p, "fp64")
+    ctrls = {"I": bd.I_CONTROLLER, "PI": bd.PI_CONTROLLER,
+             "H211PI": bd.pid_gains(1 / 3, -1 / 6, 0.0),
+             "H312PID": bd.pid_gains(2 / 9, -2 / 9, 1 / 18),
+             "PID_0.3_0.4_0.1": bd.pid_gains(0.3, 0.4, 0.1)}
+    out = {"mu": [float(m) for m in p["mu"]], "steps": {},
+           "workload": "one Van der Pol cycle per mu from (2, 0), "
+                       "atol = rtol = 1e-6, FP64 dopri5"}
+    for name, c in ctrls.items():
+        s = bd.Solver(dp, method="dopri5", precision="fp64", **c).solve()
+        st = {k: v.cpu().numpy() for k, v in s.stats().items()}
+        s.close()
+        out["steps"][name] = [int(v) for v in st["n_attempted"]]
+    torch.cuda.synchronize()
+    base = np.array(out["steps"]["I"], dtype=float)
+    out["change_vs_I_pct"] = {
+        k: [round(100.0 * (a / b - 1.0), 2) for a, b in zip(v, base)]
+        for k, v in out["steps"].items() if k != "I"}
+    print("# pid study (attempted steps per mu): " +
+          json.dumps(out["steps"]), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -359,6 +389,7 @@ def main():
     if not a.no_neural:
         line["neural"] = neural_suite(bd, W, rl, max(2, a.steps // 4),
                                       min(a.warmup, 2))
+    line["pid_study"] = pid_study(bd, W)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.method, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -92,10 +92,16 @@ typedef struct {
   /* Step-size controller (section 3: the PID family generalises the
    * integral controller; appendix C).  After an accepted step with error
    * norm err the step is scaled by
-   *   clamp(safety * err^-beta1 * err_prev^beta2, fac_min, fac_max),
-   * capped at 1 right after a rejection; after a rejected step by
-   *   max(fac_min, safety * err^-1/5).  beta2 = 0 is the integral controller;
-   * beta1 = 0.14, beta2 = 0.08 is Gustafsson's PI controller.              */
+   *   clamp(safety * err^-beta1 * err_prev^beta2 * err_prev2^beta3,
+   *         fac_min, fac_max),
+   * err_prev, err_prev2 the norms of the two previous accepted steps
+   * (clamped below at 1e-4; 1 before there were any), capped at 1 right
+   * after a rejection; after a rejected step by max(fac_min, safety *
+   * err^-1/5).  err = 0 gives fac_max.  beta2 = beta3 = 0 is the integral
+   * controller; beta1 = 0.14, beta2 = 0.08 is Gustafsson's PI controller; a
+   * PID law on log err with gains (kI, kP, kD) for an order-5 error estimate
+   * has beta1 = (kI + kP + kD)/5, beta2 = (kP + 2 kD)/5, beta3 = -kD/5.
+   * beta3 is the last member of this struct.                               */
   double beta1, beta2, safety, fac_min, fac_max;
   int32_t record_cap; /* attempted step sizes kept per instance (0: none);
                          solver_backward needs >= the largest attempt count */
@@ -107,6 +113,7 @@ typedef struct {
   int32_t ckpt_every; /* neural fields: keep y_n every ckpt_every accepted
                          steps for solver_backward (0: no checkpoints); the
                          backward recomputes the states in between          */
+  double beta3;       /* third controller exponent (PID); 0 for I and PI    */
 } bode_config;
 
 /* Problem description: device pointers (NULL where not used). */

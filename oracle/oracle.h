@@ -75,8 +75,11 @@ typedef struct {
 typedef struct {
   int32_t method;
   /* Step-size controller: on acceptance the next step is scaled by
-   * clamp(safety * err^-beta1 * err_prev^beta2, fac_min, fac_max).
-   * beta2 = 0 is the integral controller of the benchmarks.               */
+   * clamp(safety * err^-beta1 * err_prev^beta2 * err_prev2^beta3, fac_min,
+   * fac_max), err_prev and err_prev2 the error norms of the last two
+   * accepted steps (clamped below at 1e-4, 1 before there were any).
+   * beta2 = beta3 = 0 is the integral controller of the benchmarks; beta3
+   * is the PID term (set after round_state_f32, below).                    */
   double beta1, beta2, safety, fac_min, fac_max;
   int32_t max_steps;     /* attempted steps per instance                     */
   int32_t n_threads;     /* OpenMP threads (<= 0: library default)           */
@@ -106,6 +109,7 @@ typedef struct {
    * shows how strongly the trajectory amplifies float-sized perturbations
    * made at every step.                                                    */
   int32_t round_state_f32;
+  double beta3; /* third controller exponent (PID), see beta1            */
 } orc_options;
 
 /* Solves every instance.  Outputs:

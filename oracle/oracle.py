@@ -18,8 +18,17 @@ _lib_fma = None
 
 # Controller presets: the integral controller of the paper's benchmarks
 # (appendix A) and the PI controller (Gustafsson, exponents 0.7/5 and 0.4/5).
-I_CONTROLLER = dict(beta1=0.2, beta2=0.0)
-PI_CONTROLLER = dict(beta1=0.7 / 5, beta2=0.4 / 5)
+def pid_gains(k_i, k_p, k_d, order=5):
+    """Exponents of fac = err^-beta1 err_prev^beta2 err_prev2^beta3 for a PID
+    law on the logarithm of the error (Soderlind 2002):
+    log fac = -(k_i e_n + k_p (e_n - e_n-1) + k_d (e_n - 2 e_n-1 + e_n-2))
+    / order, e = log err."""
+    return dict(beta1=(k_i + k_p + k_d) / order, beta2=(k_p + 2 * k_d) / order,
+                beta3=-k_d / order)
+
+
+I_CONTROLLER = dict(beta1=0.2, beta2=0.0, beta3=0.0)
+PI_CONTROLLER = dict(beta1=0.7 / 5, beta2=0.4 / 5, beta3=0.0)
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -44,7 +53,8 @@ class _Options(C.Structure):
                 ("h_replay", _dp), ("n_replay", _ip), ("replay_cap", C.c_int32),
                 ("replay_final", _ip),
                 ("h_rec", _dp), ("rec_cap", C.c_int32), ("err_rec", _dp),
-                ("hprop_rec", _dp), ("round_state_f32", C.c_int32)]
+                ("hprop_rec", _dp), ("round_state_f32", C.c_int32),
+                ("beta3", C.c_double)]
 
 
 def _load(variant=None):
@@ -132,7 +142,8 @@ def _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
 
 
 def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
-          beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2, fac_max=10.0,
+          beta2=PI_CONTROLLER["beta2"], beta3=0.0, safety=0.9, fac_min=0.2,
+          fac_max=10.0,
           max_steps=100000, n_threads=0, h_replay=None, n_replay=None,
           record_cap=0, replay_errors=False, variant=None,
           replay_final=None, round_state_f32=False):
@@ -146,6 +157,7 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
     o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
                  n_threads)
     o.round_state_f32 = int(bool(round_state_f32))
+    o.beta3 = beta3
     if h_replay is not None:
         h_replay = _f64(h_replay)
         n_replay = np.ascontiguousarray(n_replay, dtype=np.int32)

@@ -12,11 +12,14 @@
  *    atol + rtol * max(|y_n|, |y_n+1|) (Hairer's norm, the one scipy's RK45
  *    uses); accept iff err < 1;
  *  - controller (section 3 and appendix C: PID control generalises the
- *    integral controller of the benchmarks): on acceptance
- *    fac = clamp(safety err^-beta1 err_prev^beta2, fac_min, fac_max), capped
- *    at 1 right after a rejection; on rejection
+ *    integral controller of the benchmarks; the PID acts on the logarithm
+ *    of the error, Soderlind 2002): on acceptance
+ *    fac = clamp(safety err^-beta1 err_prev^beta2 err_prev2^beta3,
+ *                fac_min, fac_max),
+ *    capped at 1 right after a rejection; on rejection
  *    fac = max(fac_min, safety err^-1/5); err == 0 gives fac_max and a
- *    non-finite err gives fac_min; err_prev = max(err, 1e-4) on acceptance;
+ *    non-finite err gives fac_min; on acceptance err_prev2 = err_prev and
+ *    err_prev = max(err, 1e-4), both 1 before the first accepted step;
  *  - start step: Hairer's rule (Solving ODEs I, II.4) unless h0 is given;
  *  - the step that reaches t_end is clipped to t_end - t and ends exactly on
  *    t_end;
@@ -173,7 +176,7 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
     else
       h = P->h0 ? P->h0[i] : hairer_start(P, i, k[0], &nfe);
 
-    double err_prev = 1.0;
+    double err_prev = 1.0, err_prev2 = 1.0;
     int prev_rejected = 0;
     while (status == ORC_RUNNING) {
       if (natt >= O->max_steps) {
@@ -227,7 +230,8 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
             fac = O->fac_max;
           else
             fac = clampd(O->safety * pow(err, -O->beta1) *
-                             pow(err_prev, O->beta2),
+                             pow(err_prev, O->beta2) *
+                             pow(err_prev2, O->beta3),
                          O->fac_min, O->fac_max);
           if (prev_rejected) fac = fmin(1.0, fac);
         } else {
@@ -252,6 +256,7 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
         if (O->round_state_f32)
           for (int c = 0; c < n; ++c) y[c] = (double)(float)y[c];
         memcpy(k[0], k[6], sizeof(double) * n); /* FSAL */
+        err_prev2 = err_prev;
         err_prev = fmax(err, 1e-4);
         nacc += 1;
         prev_rejected = 0;

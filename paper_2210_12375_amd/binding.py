@@ -24,8 +24,15 @@ METHODS = {"dopri5": DOPRI5, "tsit5": TSIT5}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 # Controller presets: integral (the paper's benchmarks, appendix A) and
 # Gustafsson's PI controller.
-I_CONTROLLER = dict(beta1=0.2, beta2=0.0)
-PI_CONTROLLER = dict(beta1=0.7 / 5, beta2=0.4 / 5)
+I_CONTROLLER = dict(beta1=0.2, beta2=0.0, beta3=0.0)
+PI_CONTROLLER = dict(beta1=0.7 / 5, beta2=0.4 / 5, beta3=0.0)
+
+
+def pid_gains(k_i, k_p, k_d, order=5):
+    """Controller exponents (beta1, beta2, beta3) of a PID law on the log of
+    the error norm with gains (k_i, k_p, k_d)."""
+    return dict(beta1=(k_i + k_p + k_d) / order, beta2=(k_p + 2 * k_d) / order,
+                beta3=-k_d / order)
 
 EXPORTED = ["solver_workspace_size", "solver_init", "solver_step",
             "solver_solve", "solver_eval", "solver_backward",
@@ -42,7 +49,7 @@ class Config(C.Structure):
                 ("fac_max", C.c_double), ("record_cap", C.c_int32),
                 ("keep_dense", C.c_int32), ("mlp_hidden", C.c_int32),
                 ("tune_block", C.c_int32), ("tune_lanes", C.c_int32),
-                ("ckpt_every", C.c_int32)]
+                ("ckpt_every", C.c_int32), ("beta3", C.c_double)]
 
 
 _PROBLEM_FIELDS = ["y0", "t0", "t_end", "rtol", "atol", "t_eval", "h0", "kind",
@@ -113,7 +120,7 @@ def make_config(B, D, E=0, method="dopri5", precision="fp64",
                 rhs=RHS_ANALYTIC, max_steps=100000, beta1=PI_CONTROLLER["beta1"],
                 beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2,
                 fac_max=10.0, record_cap=0, keep_dense=0, mlp_hidden=0,
-                tune_block=0, tune_lanes=0, ckpt_every=0):
+                tune_block=0, tune_lanes=0, ckpt_every=0, beta3=0.0):
     c = Config()
     c.method = METHODS[method] if isinstance(method, str) else method
     c.precision = (PRECISIONS[precision] if isinstance(precision, str)
@@ -124,6 +131,7 @@ def make_config(B, D, E=0, method="dopri5", precision="fp64",
     c.record_cap, c.keep_dense, c.mlp_hidden = record_cap, keep_dense, mlp_hidden
     c.tune_block, c.tune_lanes = tune_block, tune_lanes
     c.ckpt_every = ckpt_every
+    c.beta3 = beta3
     return c
 
 

@@ -83,7 +83,7 @@ struct Lane {
   // next_te is the instance's next evaluation time, next_te2 the one after:
   // it is fetched one emission early, so an emission never waits on memory.
   double t, te, next_te, next_te2;
-  R h, err_prev, rtol, atol;
+  R h, err_prev, err_prev2, rtol, atol;
   int32_t n_att, n_acc, n_rej, n_fe, status, cursor, prev_rej, dim, inst;
 };
 
@@ -120,6 +120,7 @@ __device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<
   L.te = a.t_end[i];
   L.h = s.h[i];
   L.err_prev = s.err_prev[i];
+  L.err_prev2 = s.err_prev2[i];
   L.rtol = R(a.rtol[i]);
   L.atol = R(a.atol[i]);
   L.n_att = s.n_att[i];
@@ -148,6 +149,7 @@ __device__ __forceinline__ void store_lane(const AnalyticArgs<R>& a, const Lane<
   s.t[i] = L.t;
   s.h[i] = L.h;
   s.err_prev[i] = L.err_prev;
+  s.err_prev2[i] = L.err_prev2;
   s.n_att[i] = L.n_att;
   s.n_acc[i] = L.n_acc;
   s.n_rej[i] = L.n_rej;
@@ -228,20 +230,28 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
     a.h_rec[(long)L.inst * a.rec_cap + L.n_att - 1] =
         accept ? double(hs) : -double(hs);
 
-  // Controller: on acceptance clamp(safety err^-beta1 err_prev^beta2), capped
-  // at 1 after a rejection; on rejection max(fac_min, safety err^-1/5); a
-  // non-finite err gives fac_min (err = 0 reaches fac_max through the clamp).
-  // L.err_prev holds err_prev^beta2, formed when that step was accepted.
+  // Controller: on acceptance
+  // clamp(safety err^-beta1 err_prev^beta2 err_prev2^beta3), capped at 1
+  // after a rejection; on rejection max(fac_min, safety err^-1/5); err = 0
+  // gives fac_max, a non-finite err fac_min.  The error history holds the
+  // clamped norms of the two previous accepted steps (FP64) or log2 of their
+  // clamped squares (FP32), 1 / 0 initially.
   const Ctrl& c = a.ctrl;
-  R pw, lg = R(0);
-  if constexpr (kSq) {
+  R fac, lg = R(0);
+  if constexpr (kSq) {  // one exp2 for the whole factor
     lg = __builtin_amdgcn_logf(err2);  // log2
-    pw = __builtin_amdgcn_exp2f(lg * (accept ? R(-0.5 * c.beta1) : R(-0.1)));
+    const R ex = accept ? R(-0.5 * c.beta1) * lg + R(0.5 * c.beta2) * L.err_prev +
+                              R(0.5 * c.beta3) * L.err_prev2
+                        : R(-0.1) * lg;
+    fac = R(c.safety) * __builtin_amdgcn_exp2f(ex);
   } else {
-    pw = ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
+    fac = R(c.safety) * ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
+    if (accept) {
+      if (c.beta2 != 0.0) fac = fac * ctl_pow(L.err_prev, R(c.beta2));
+      if (c.beta3 != 0.0) fac = fac * ctl_pow(L.err_prev2, R(c.beta3));
+    }
   }
-  R fac = R(c.safety) * pw;
-  fac = accept ? fac * L.err_prev : fac;
+  fac = (accept && err == R(0)) ? R(c.fac_max) : fac;
   fac = rmax(R(c.fac_min), accept ? rmin(R(c.fac_max), fac) : fac);
   fac = (accept && L.prev_rej) ? rmin(R(1), fac) : fac;
   fac = __builtin_isfinite(err) ? fac : R(c.fac_min);
@@ -298,16 +308,11 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
     }
     L.t = tnew;
     if (last) L.status = kSuccess;
-    if constexpr (kSq)  // max(err, 1e-4)^beta2 = 2^(beta2/2 max(lg, log2 1e-8))
-      L.err_prev = c.beta2 != 0.0
-                       ? __builtin_amdgcn_exp2f(
-                             R(0.5 * c.beta2) *
-                             rmax(lg, R(-26.575424759098897)))
-                       : R(1);
+    L.err_prev2 = L.err_prev;
+    if constexpr (kSq)  // log2 max(err, 1e-4)^2 = max(lg, log2 1e-8)
+      L.err_prev = rmax(lg, R(-26.575424759098897));
     else
-      L.err_prev = c.beta2 != 0.0
-                       ? ctl_pow(rmax(err, R(1e-4)), R(c.beta2))
-                       : R(1);
+      L.err_prev = rmax(err, R(1e-4));
     L.n_acc += 1;
   }
   L.n_rej += accept ? 0 : 1;
@@ -455,7 +460,7 @@ __device__ __forceinline__ void init_one(const AnalyticArgs<R>& a, int i) {
   L.n_fe = 1;
   L.n_att = L.n_acc = L.n_rej = 0;
   L.prev_rej = 0;
-  L.err_prev = R(1);
+  L.err_prev = L.err_prev2 = std::is_same<R, float>::value ? R(0) : R(1);
   L.cursor = 0;
   while (L.cursor < a.E && a.t_eval[(long)i * a.E + L.cursor] <= L.t) {
     write_row<R, N>(a.y_eval + ((long)i * a.E + L.cursor) * a.D, a.D, L.y,

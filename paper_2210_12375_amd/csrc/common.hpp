@@ -22,6 +22,7 @@ enum : int32_t { kKindVdp = 0, kKindLinear = 1 };
 struct Ctrl {
   double beta1, beta2, safety, fac_min, fac_max;
   int32_t max_steps;
+  double beta3;
 };
 
 // Per-instance solver state kept in the caller's workspace between calls
@@ -30,7 +31,11 @@ template <typename R>
 struct State {
   double* t;         // current time
   R* h;              // next step size to try
-  R* err_prev;       // err_prev^beta2 of the last accepted step (PI term)
+  // error history of the last two accepted steps (PI and PID terms): the
+  // norms clamped below at 1e-4, or in the squared-norm FP32 controller of
+  // the analytic kernels log2 of the clamped squared norms
+  R* err_prev;
+  R* err_prev2;
   int32_t* n_att;    // attempted steps
   int32_t* n_acc;    // accepted steps
   int32_t* n_rej;    // rejected steps

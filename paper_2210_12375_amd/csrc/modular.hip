@@ -46,7 +46,7 @@ struct Mod {
   const R *W1, *b1, *W2, *b2, *W3, *b3, *eps;
   R* y_eval;
   R* y_final;
-  State<R> st;     // t, h, err_prev^beta2, counters, status, cursor, y, k1
+  State<R> st;     // t, h, error history, counters, status, cursor, y, k1
   R* K;            // [7, B, D] stages (K[0] = k1 = st.k1)
   R* Y7;           // [B, D] stage-7 input = candidate solution
   R* hs;           // [B] size of the current attempt
@@ -343,6 +343,7 @@ __global__ void mod_init_rows(Mod<R> m) {
     st.n_fe[row] = ok ? 1 : 0;
     st.prev_rej[row] = 0;
     st.err_prev[row] = R(1);
+    st.err_prev2[row] = R(1);
     st.t[row] = t0;
     st.h[row] = R(0);
     m.hs[row] = R(0);
@@ -482,7 +483,11 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
   const Ctrl& c = m.ctrl;
   const R pw = ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
   R fac = R(c.safety) * pw;
-  fac = accept ? fac * m.st.err_prev[row] : fac;
+  if (accept) {  // PI and PID terms of the two previous accepted steps
+    if (c.beta2 != 0.0) fac = fac * ctl_pow(m.st.err_prev[row], R(c.beta2));
+    if (c.beta3 != 0.0) fac = fac * ctl_pow(m.st.err_prev2[row], R(c.beta3));
+  }
+  fac = (accept && err == R(0)) ? R(c.fac_max) : fac;
   fac = rmax(R(c.fac_min), accept ? rmin(R(c.fac_max), fac) : fac);
   fac = (accept && m.st.prev_rej[row]) ? rmin(R(1), fac) : fac;
   fac = __builtin_isfinite(err) ? fac : R(c.fac_min);
@@ -548,8 +553,8 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
     if (last) status = kSuccess;
     if (lane == 0) {
       m.st.cursor[row] = cursor;
-      m.st.err_prev[row] =
-          c.beta2 != 0.0 ? ctl_pow(rmax(err, R(1e-4)), R(c.beta2)) : R(1);
+      m.st.err_prev2[row] = m.st.err_prev[row];
+      m.st.err_prev[row] = rmax(err, R(1e-4));
       m.st.n_acc[row] += 1;
     }
   }
@@ -712,6 +717,7 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
   st.t = L.take<double>(B);
   st.h = L.take<R>(B);
   st.err_prev = L.take<R>(B);
+  st.err_prev2 = L.take<R>(B);
   st.n_att = L.take<int32_t>(B);
   st.n_acc = L.take<int32_t>(B);
   st.n_rej = L.take<int32_t>(B);
@@ -829,7 +835,7 @@ void fill_mod(Mod<R>* m, const bode_config& c, const bode_problem& p) {
   m->y_eval = static_cast<R*>(p.y_eval);
   m->y_final = static_cast<R*>(p.y_final);
   m->ctrl = Ctrl{c.beta1, c.beta2, c.safety, c.fac_min, c.fac_max,
-                 c.max_steps};
+                 c.max_steps, c.beta3};
 }
 
 template <typename R>

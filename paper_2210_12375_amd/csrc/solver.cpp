@@ -119,10 +119,12 @@ std::string check_config(const bode_config* c) {
   if (c->E < 0) return "E must be >= 0";
   if (c->max_steps < 1) return "max_steps must be >= 1";
   if (!(c->safety > 0.0) || !(c->fac_min > 0.0) || !(c->fac_min <= 1.0) ||
-      !(c->fac_max >= 1.0) || !(c->beta1 >= 0.0) || !(c->beta2 >= 0.0) ||
-      !std::isfinite(c->fac_max) || !std::isfinite(c->safety))
+      !(c->fac_max >= 1.0) || !(c->beta1 >= 0.0) ||
+      !std::isfinite(c->beta1) || !std::isfinite(c->beta2) ||
+      !std::isfinite(c->beta3) || !std::isfinite(c->fac_max) ||
+      !std::isfinite(c->safety))
     return "controller needs safety > 0, 0 < fac_min <= 1 <= fac_max, "
-           "beta1, beta2 >= 0";
+           "finite beta1 >= 0, finite beta2 and beta3";
   if (c->record_cap < 0) return "record_cap must be >= 0";
   if (c->ckpt_every < 0) return "ckpt_every must be >= 0";
   if (c->ckpt_every > 0 && c->record_cap < 1)
@@ -144,6 +146,7 @@ size_t layout_analytic(const bode_config& c, void* base,
   st.t = L.take<double>(B);
   st.h = L.take<R>(B);
   st.err_prev = L.take<R>(B);
+  st.err_prev2 = L.take<R>(B);
   st.n_att = L.take<int32_t>(B);
   st.n_acc = L.take<int32_t>(B);
   st.n_rej = L.take<int32_t>(B);
@@ -207,7 +210,7 @@ void fill_analytic_args(bode_solver* s, bode::AnalyticArgs<R>* a) {
   a->y_eval = static_cast<R*>(p.y_eval);
   a->y_final = static_cast<R*>(p.y_final);
   a->ctrl = bode::Ctrl{c.beta1, c.beta2, c.safety, c.fac_min, c.fac_max,
-                       c.max_steps};
+                       c.max_steps, c.beta3};
   a->budget = c.max_steps + 1;
 }
 

@@ -172,3 +172,31 @@ def paper_vdp(seed=6, B=256, mu=2.0, E=200, tol=1e-5, period=7.6295):
     p["rtol"][:] = tol
     p["atol"][:] = tol
     return p
+
+
+def vdp_period(mu):
+    """Approximate period of Van der Pol's limit cycle: 2 pi (1 + mu^2/16)
+    for mu < 1, else the leading relaxation terms (3 - 2 ln 2) mu +
+    7.014 mu^(-1/3)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    small = 2 * np.pi * (1 + mu ** 2 / 16)
+    large = (3 - 2 * np.log(2)) * mu + 7.014 * np.maximum(mu, 1e-12) ** (-1 / 3)
+    return np.where(mu < 1, small, large)
+
+
+def vdp_cycles(mus=(0.0, 1.0, 2.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0, 40.0,
+                    50.0), tol=1e-6):
+    """One cycle of Van der Pol's oscillator per damping strength mu (the
+    controller study of appendix C): state (2, 0) near the limit cycle,
+    t in [0, vdp_period(mu)], atol = rtol = tol, final state only."""
+    mus = np.asarray(mus, dtype=np.float64)
+    B = mus.size
+    p = _base(B, 2, 0)
+    p["mu"] = mus.copy()
+    p["y0"][:] = np.array([2.0, 0.0])
+    p["t_end"][:] = vdp_period(mus)
+    p["kind"][:] = VDP
+    p["dim"][:] = 2
+    p["rtol"][:] = tol
+    p["atol"][:] = tol
+    return p

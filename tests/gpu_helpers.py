@@ -60,7 +60,18 @@ def run_gpu(p, method="dopri5", precision="fp64", rhs=bd.RHS_ANALYTIC, **kw):
     return out, s
 
 
+# PID presets on log err: Soderlind's H211PI and H312PID digital filters
+# (2003) in gain form, and a PID with a positive derivative gain.
+PID_CONTROLLERS = {
+    "H211PI": bd.pid_gains(1 / 3, -1 / 6, 0.0),
+    "H312PID": bd.pid_gains(2 / 9, -2 / 9, 1 / 18),
+    "PID": bd.pid_gains(0.3, 0.4, 0.1),
+}
+
+
 def controller(ctrl):
+    if ctrl in PID_CONTROLLERS:
+        return PID_CONTROLLERS[ctrl]
     return bd.I_CONTROLLER if ctrl == "I" else bd.PI_CONTROLLER
 
 

@@ -28,7 +28,7 @@ def flush(msg):
 
 
 @pytest.mark.parametrize("method", METHODS)
-@pytest.mark.parametrize("ctrl", ["PI", "I"])
+@pytest.mark.parametrize("ctrl", ["PI", "I", "H312PID", "PID"])
 def test_vdp64_fp64_parity(method, ctrl):
     flush(f"vdp64 fp64 {method} {ctrl}")
     p = W.vdp_batch()
@@ -39,7 +39,7 @@ def test_vdp64_fp64_parity(method, ctrl):
 
 
 @pytest.mark.parametrize("method", METHODS)
-@pytest.mark.parametrize("ctrl", ["PI", "I"])
+@pytest.mark.parametrize("ctrl", ["PI", "I", "H211PI"])
 def test_uneven_short_horizon_exact(method, ctrl):
     """The uneven batch over short horizons (t_end / 12.5), where every step
     is accuracy-limited: identical counts and statuses for every instance,
@@ -259,3 +259,24 @@ def test_autotune_keeps_results():
                     tune_lanes=4096)
     np.testing.assert_array_equal(g1["y_final"], g2["y_final"])
     np.testing.assert_array_equal(g1["n_accepted"], g2["n_accepted"])
+
+
+@pytest.mark.parametrize("ctrl", ["H312PID", "PID"])
+def test_pid_fp32_replay(ctrl):
+    """FP32 with a PID controller (one exp2 for the whole factor): the
+    oracle replays the GPU's attempt record within the FP32 bound."""
+    flush(f"vdp fp32 {ctrl}")
+    p = W.vdp_batch(B=256)
+    c = controller(ctrl)
+    g, _ = run_gpu(p, method="dopri5", precision="fp32", record_cap=4096, **c)
+    assert np.all(g["status"] == bd.SUCCESS)
+    q = as_float_inputs(p)
+    r = oracle_replay(q, g, "dopri5")
+    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
+                                       r["y_final"])
+    rel = diff / np.maximum(scale, np.abs(q["y0"]).max(axis=1))
+    assert np.mean(rel <= TOL_FP32) >= 0.99, np.sort(rel)[-5:]
+    f = oracle.solve(q, method="dopri5", **c)
+    flush(f"  steps {g['n_accepted'].mean():.1f} vs FP64 "
+          f"{f['n_accepted'].mean():.1f}")
+    assert abs(g["n_accepted"].mean() / f["n_accepted"].mean() - 1) < 0.02

@@ -205,3 +205,15 @@ def test_fused_solve_slices_and_edges(precision):
     np.testing.assert_array_equal(k["n_attempted"], g["n_attempted"])
     np.testing.assert_allclose(k["y_final"][ok], g["y_final"][ok], rtol=0,
                                atol=1e-5 * np.abs(g["y_final"][ok]).max())
+
+
+def test_mlp_fp64_pid_parity():
+    """A PID controller on a neural field (the per-stage FP64 path)."""
+    flush("mlp fp64 pid")
+    c = bd.pid_gains(0.3, 0.4, 0.1)
+    p = W.neural_ode(B=64)
+    g, _ = run_gpu(p, method="dopri5", rhs=bd.RHS_MLP, record_cap=256, **c)
+    r = oracle.solve(p, method="dopri5", **c)
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
+    replay_check(p, g, "dopri5", c)

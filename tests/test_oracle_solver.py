@@ -14,7 +14,7 @@ from scipy.integrate._ivp.common import select_initial_step
 from scipy.linalg import expm
 
 import oracle
-from oracle.oracle import I_CONTROLLER, PI_CONTROLLER
+from oracle.oracle import I_CONTROLLER, PI_CONTROLLER, pid_gains
 from paper_2210_12375_amd import workloads as W
 
 METHODS = ["dopri5", "tsit5"]
@@ -230,27 +230,50 @@ def test_initial_step_is_hairers_rule():
         assert abs(h - ref) <= 1e-14 * ref
 
 
-@pytest.mark.parametrize("ctrl,beta", [("I", (0.2, 0.0)),
-                                       ("PI", (0.7 / 5, 0.4 / 5)),
-                                       ("PI2", (0.15, 0.05))])
+_H211PI = pid_gains(1 / 3, -1 / 6, 0.0)
+_H312PID = pid_gains(2 / 9, -2 / 9, 1 / 18)
+
+
+@pytest.mark.parametrize("ctrl,beta", [
+    ("I", (0.2, 0.0, 0.0)),
+    ("PI", (0.7 / 5, 0.4 / 5, 0.0)),
+    ("PI2", (0.15, 0.05, 0.0)),
+    ("H211PI", tuple(_H211PI[k] for k in ("beta1", "beta2", "beta3"))),
+    ("H312PID", tuple(_H312PID[k] for k in ("beta1", "beta2", "beta3"))),
+    ("PID", (0.2, 0.1, -0.02)),
+])
 def test_controller_steady_state(ctrl, beta):
     """On y' = -y with atol = 0 the error of a step depends only on h, so the
-    controller settles where safety * err^(beta2 - beta1) = 1, i.e. at
-    err* = safety^(1 / (beta1 - beta2)).  A dropped or sign-flipped term moves
-    this fixed point."""
-    b1, b2 = beta
+    controller settles where safety * err^(beta2 + beta3 - beta1) = 1, i.e. at
+    err* = safety^(1 / (beta1 - beta2 - beta3)).  A dropped or sign-flipped
+    term moves this fixed point."""
+    b1, b2, b3 = beta
     p = dict(kind=np.full(1, W.LINEAR, np.int32), dim=np.ones(1, np.int32),
              y0=np.ones((1, 1)), t0=np.zeros(1), t_end=np.full(1, 40.0),
              rtol=np.full(1, 1e-6), atol=np.zeros(1), A=-np.ones((1, 1, 1)))
-    r = oracle.solve(p, method="dopri5", beta1=b1, beta2=b2, record_cap=4000)
+    r = oracle.solve(p, method="dopri5", beta1=b1, beta2=b2, beta3=b3,
+                     record_cap=20000)
     hacc, nacc = oracle.accepted_steps(r["h_rec"], r["n_attempted"])
     h = hacc[0, nacc[0] - 5]  # well before the clipped last step
     c, A, b, bh = oracle.tableau("dopri5")
     z = -h
     stage = np.linalg.solve(np.eye(7) - z * A, np.ones(7))  # k_j / (lam y_n)
     err = abs(z * (b - bh) @ stage) / 1e-6
-    target = 0.9 ** (1.0 / (b1 - b2))
+    target = 0.9 ** (1.0 / (b1 - b2 - b3))
     assert abs(err / target - 1.0) < 0.02, (err, target)
+
+
+def test_pid_gains_map_to_the_known_controllers():
+    """The PID-on-log-error parametrisation gives the integral controller for
+    gains (1, 0, 0) and Gustafsson's PI (exponents 0.7/5, 0.4/5) for
+    (0.3, 0.4, 0); a derivative gain enters all three exponents."""
+    for g, ref in (((1.0, 0.0, 0.0), I_CONTROLLER),
+                   ((0.3, 0.4, 0.0), PI_CONTROLLER)):
+        got = pid_gains(*g)
+        for k in ("beta1", "beta2", "beta3"):
+            assert abs(got[k] - ref[k]) < 1e-15, (g, k)
+    d = pid_gains(0.0, 0.0, 1.0)
+    assert (d["beta1"], d["beta2"], d["beta3"]) == (0.2, 0.4, -0.2)
 
 
 def test_constant_field_grows_steps_by_fac_max():
@@ -370,3 +393,16 @@ def test_float_rounding_probe_is_float_sized():
     rel = np.abs(rp["y_final"] - rr["y_final"]).max(axis=1) / \
         np.abs(rr["y_final"]).max(axis=1)
     assert np.all(rel > 1e-12) and np.all(rel < 1e-4), rel
+
+
+def test_pid_study_shape_of_appendix_c():
+    """Appendix C: over one Van der Pol cycle, PID-family controllers take
+    more steps than the integral controller when the step size varies
+    little (small mu) and save steps once the cycle is stiff (mu > 25)."""
+    p = W.vdp_cycles(mus=(0.0, 5.0, 10.0, 30.0, 40.0, 50.0))
+    i = oracle.solve(p, method="dopri5", **I_CONTROLLER)["n_attempted"]
+    for c in (PI_CONTROLLER, pid_gains(0.3, 0.4, 0.1)):
+        n = oracle.solve(p, method="dopri5", **c)["n_attempted"]
+        assert np.all(n[:3] > i[:3]), (n, i)
+        saving = 1.0 - n[3:] / i[3:]
+        assert np.all(saving > 0.02), (n, i)
