@@ -145,6 +145,17 @@ void orc_dense_weights(int32_t method, double theta, double* w);
 /* Hairer's starting step for instance i (returns h, adds f-evals to *nfe). */
 double orc_initial_step(const orc_problem* P, int32_t i, int32_t* nfe);
 
+/* 1 if instance i passes the input checks of an independent solve.        */
+int orc_instance_valid(const orc_problem* P, int32_t i);
+
+/* Joint (coupled) solve of section 4.1: the members (valid instances with
+ * the first valid instance's t0, t_end, t_eval and h0) form one system with
+ * a single step size, error norm and accept/reject decision (joint.c).
+ * Outputs as orc_solve; every member reports the joint counts.  The
+ * options' replay and recording fields are not used.                        */
+int orc_solve_joint(const orc_problem* P, const orc_options* O,
+                    double* y_eval, double* y_final, int32_t* stats);
+
 #ifdef __cplusplus
 }
 #endif

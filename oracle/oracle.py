@@ -65,6 +65,8 @@ def _load(variant=None):
             lib = C.CDLL(_build.LIB_FMA)
             lib.orc_solve.restype = C.c_int
             lib.orc_solve.argtypes = _lib.orc_solve.argtypes
+            lib.orc_solve_joint.restype = C.c_int
+            lib.orc_solve_joint.argtypes = _lib.orc_solve.argtypes
             _lib_fma = lib
         return _lib_fma
     if _lib is None:
@@ -74,6 +76,8 @@ def _load(variant=None):
         lib.orc_solve.restype = C.c_int
         lib.orc_solve.argtypes = [C.POINTER(_Problem), C.POINTER(_Options),
                                   _dp, _dp, _ip]
+        lib.orc_solve_joint.restype = C.c_int
+        lib.orc_solve_joint.argtypes = lib.orc_solve.argtypes
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint.argtypes = [C.POINTER(_Problem), C.POINTER(_Options),
                                     _dp, _ip, C.c_int32, _dp, _dp, _dp, _dp]
@@ -191,6 +195,27 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
         out["err_rec"] = err_rec
         out["hprop_rec"] = hprop
     return out
+
+
+def solve_joint(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
+                beta2=PI_CONTROLLER["beta2"], beta3=0.0, safety=0.9,
+                fac_min=0.2, fac_max=10.0, max_steps=100000, variant=None):
+    """Joint (coupled) solve of section 4.1: the batch as one stacked system
+    with one step size and one error norm; returns the arrays of solve()."""
+    lib = _load(variant)
+    m = _Marshalled(problem)
+    o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps, 0)
+    o.beta3 = beta3
+    y_eval = np.zeros((m.B, m.E, m.D))
+    y_final = np.zeros((m.B, m.D))
+    stats = np.zeros((5, m.B), dtype=np.int32)
+    rc = lib.orc_solve_joint(C.byref(m.s), C.byref(o), _ptr(y_eval),
+                             _ptr(y_final), _ptr(stats, _ip))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem description")
+    return dict(y_eval=y_eval, y_final=y_final, n_attempted=stats[0],
+                n_accepted=stats[1], n_rejected=stats[2], n_feval=stats[3],
+                status=stats[4])
 
 
 def accepted_steps(h_rec, n_attempted):

@@ -90,7 +90,7 @@ double orc_initial_step(const orc_problem* P, int32_t i, int32_t* nfe) {
   return h;
 }
 
-static int instance_valid(const orc_problem* P, int32_t i) {
+int orc_instance_valid(const orc_problem* P, int32_t i) {
   const int n = P->dim[i];
   if (n < 1 || n > P->D) return 0;
   if (P->kind[i] < ORC_RHS_VDP || P->kind[i] > ORC_RHS_CNF_DIAG) return 0;
@@ -136,7 +136,7 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
   for (long q = 0; q < D; ++q) yfin[q] = (q < n) ? NAN : 0.0;
 
   int32_t natt = 0, nacc = 0, nrej = 0, nfe = 0, status = ORC_RUNNING;
-  if (!instance_valid(P, i)) {
+  if (!orc_instance_valid(P, i)) {
     status = ORC_INVALID;
     goto done;
   }

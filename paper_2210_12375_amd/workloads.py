@@ -200,3 +200,43 @@ def vdp_cycles(mus=(0.0, 1.0, 2.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0, 40.0,
     p["rtol"][:] = tol
     p["atol"][:] = tol
     return p
+
+
+def vdp_phases(seed=7, B=64, mu=25.0, tol=1e-6, E=0):
+    """Section 4.1's batch: B Van der Pol oscillators with the same damping
+    mu, each started at a different phase of its limit cycle (the state
+    after a uniformly drawn fraction of a cycle from (2, 0)), integrated over
+    one cycle; atol = rtol = tol.  The phase points come from marching (2, 0)
+    along the cycle with small forward-Euler steps (they only need to be
+    spread over the cycle, not exact)."""
+    rng = np.random.default_rng(seed)
+    T = float(vdp_period(mu))
+    frac = rng.uniform(0.0, 1.0, B)
+    # march (2, 0) along the cycle with small explicit steps to the phases
+    n = 200000
+    dt = T / n
+    x, v = 2.0, 0.0
+    marks = np.sort(frac) * T
+    order = np.argsort(frac)
+    y0 = np.zeros((B, 2))
+    t, m = 0.0, 0
+    for step in range(n + 1):
+        while m < B and marks[m] <= t + 0.5 * dt:
+            y0[order[m]] = (x, v)
+            m += 1
+        if m == B:
+            break
+        a = mu * (1 - x * x) * v - x
+        x, v = x + dt * v, v + dt * a
+        t += dt
+    p = _base(B, 2, E)
+    p["mu"] = np.full(B, mu)
+    p["y0"][:] = y0
+    p["t_end"][:] = T
+    if E:
+        p["t_eval"][:] = np.linspace(0.0, T, E)[None, :]
+    p["kind"][:] = VDP
+    p["dim"][:] = 2
+    p["rtol"][:] = tol
+    p["atol"][:] = tol
+    return p
