@@ -280,6 +280,34 @@ def pid_study(bd, W):
     return out
 
 
+def joint_study(bd, W):
+    """Section 4.1: attempted steps of a joint (coupled) solve of B Van der
+    Pol oscillators at different phases against the independent solve of
+    the same batch (FP64 Dormand-Prince on the GPU)."""
+    import torch
+    rows = []
+    for mu in (5.0, 10.0, 25.0, 50.0):
+        for B in (4, 16, 64):
+            p = W.vdp_phases(B=B, mu=mu)
+            dp = bd.device_problem(p, "fp64")
+            out = {}
+            for joint in (0, 1):
+                s = bd.Solver(dp, method="dopri5", precision="fp64",
+                              joint=joint).solve()
+                out[joint] = s.stats()["n_attempted"].cpu().numpy()
+                s.close()
+            torch.cuda.synchronize()
+            rows.append(dict(mu=mu, B=B, joint=int(out[1][0]),
+                             independent_mean=float(out[0].mean()),
+                             independent_max=int(out[0].max()),
+                             ratio=round(float(out[1][0] / out[0].mean()), 2)))
+    print("# joint study (joint / independent attempted steps): " +
+          ", ".join(f"mu={r['mu']:g} B={r['B']}: {r['ratio']}" for r in rows),
+          file=sys.stderr, flush=True)
+    return {"rows": rows, "workload": "B Van der Pol oscillators at uniformly "
+            "drawn phases of one cycle, atol = rtol = 1e-6, FP64 dopri5"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -390,6 +418,7 @@ def main():
         line["neural"] = neural_suite(bd, W, rl, max(2, a.steps // 4),
                                       min(a.warmup, 2))
     line["pid_study"] = pid_study(bd, W)
+    line["joint_study"] = joint_study(bd, W)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.method, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -114,6 +114,14 @@ typedef struct {
                          steps for solver_backward (0: no checkpoints); the
                          backward recomputes the states in between          */
   double beta3;       /* third controller exponent (PID); 0 for I and PI    */
+  int32_t joint;      /* 1: joint (coupled) batch mode of section 4.1, the
+                         comparison mode: the members (valid instances with
+                         the first valid instance's t0, t_end, t_eval and h0;
+                         the others are BODE_INVALID) are solved as one
+                         system with one step size, one error norm (RMS over
+                         all their components) and one accept/reject
+                         decision.  ANALYTIC fields, record_cap = 0 and
+                         keep_dense = 0 only.  0: independent instances.   */
 } bode_config;
 
 /* Problem description: device pointers (NULL where not used). */

@@ -544,6 +544,369 @@ __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
 
 // ---- launchers -----------------------------------------------------------------
 
+// ---- joint (coupled) mode -----------------------------------------------------
+//
+// Section 4.1's comparison mode: the members (valid instances with the first
+// valid instance's t0, t_end, evaluation times and h0) are one system of
+// size sum(dim) with one time, step size, error norm (weighted RMS over all
+// their components, each scaled by its own instance's tolerances) and
+// accept/reject decision.  One workgroup owns the batch: each thread runs
+// its instances' stages in registers, their scaled squared errors meet in a
+// block reduction (fixed order), thread 0 takes the decision and the
+// controller step, and the threads commit their instances.
+
+constexpr int kJointThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ T joint_sum(T v, T* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  T acc = T(0);
+  for (int q = 0; q < kJointThreads / 64; ++q) acc += red[q];
+  return acc;
+}
+
+template <typename R>
+__device__ __forceinline__ bool joint_member(const AnalyticArgs<R>& a, int i,
+                                             int ref) {
+  if (a.st.status[i] == kInvalid) return false;
+  if (a.t0[i] != a.t0[ref] || a.t_end[i] != a.t_end[ref]) return false;
+  for (int e = 0; e < a.E; ++e)
+    if (a.t_eval[(long)i * a.E + e] != a.t_eval[(long)ref * a.E + e])
+      return false;
+  if (a.h0 != nullptr && a.h0[i] != a.h0[ref]) return false;
+  return true;
+}
+
+// Stages 2..7 of member i from (t, y_i, k1_i) with step hs: k_2..k_7 and
+// the candidate solution go to the workspace; returns the instance's sum
+// of squared scaled errors.
+template <typename R, class M, class F>
+__device__ R joint_stages(const AnalyticArgs<R>& a, int i, double t, R hs) {
+  constexpr int N = F::N;
+  F f;
+  const int dim = a.dim[i];
+  f.load(a, i, dim);
+  const long B = a.B, D = a.D;
+  R y[N], k[7][N], Y[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    y[q] = q < dim ? a.st.y[i * D + q] : R(0);
+    k[0][q] = q < dim ? a.st.k1[i * D + q] : R(0);
+  }
+  (void)t;  // the analytic fields are autonomous
+#pragma unroll
+  for (int s = 1; s < 7; ++s) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R acc = R(0);
+#pragma unroll
+      for (int j = 0; j < s; ++j)
+        if (M::A[s][j] != 0.0) acc += R(M::A[s][j]) * k[j][q];
+      Y[q] = y[q] + hs * acc;
+    }
+    f(Y, k[s]);
+  }
+  R e2 = R(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    if (q >= dim) continue;
+    R eq = R(0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+      if (M::E[j] != 0.0) eq += R(M::E[j]) * k[j][q];
+    eq *= hs;
+    const R sc = R(a.atol[i]) + R(a.rtol[i]) * rmax(rabs(y[q]), rabs(Y[q]));
+    const R r = eq / sc;
+    e2 += r * r;
+    a.jY[i * D + q] = Y[q];
+#pragma unroll
+    for (int s = 1; s < 7; ++s) a.jK[((s - 1) * B + i) * D + q] = k[s][q];
+  }
+  return e2;
+}
+
+template <typename R>
+__device__ void joint_write_stats(const AnalyticArgs<R>& a, int i,
+                                  const JointState& j) {
+  a.st.n_att[i] = j.n_att;
+  a.st.n_acc[i] = j.n_acc;
+  a.st.n_rej[i] = j.n_rej;
+  a.st.n_fe[i] = 1 + j.probe + 6 * j.n_att;
+  a.st.status[i] = j.status;
+  a.st.t[i] = j.t;
+  a.st.h[i] = R(j.h);
+  a.st.cursor[i] = j.cursor;
+}
+
+template <typename R>
+__device__ void joint_finish(const AnalyticArgs<R>& a, int i,
+                             const JointState& j) {
+  const int dim = a.dim[i];
+  for (int q = 0; q < a.D; ++q)
+    a.y_final[(long)i * a.D + q] =
+        q < dim ? a.st.y[(long)i * a.D + q] : R(0);
+  if (j.status != kSuccess)
+    for (int e = j.cursor; e < a.E; ++e)
+      for (int q = 0; q < a.D; ++q)
+        a.y_eval[((long)i * a.E + e) * a.D + q] =
+            q < dim ? quiet_nan<R>() : R(0);
+}
+
+template <typename R>
+__device__ void joint_rhs(const AnalyticArgs<R>& a, int i, const R* y, R* f) {
+  if (a.kind[i] == kKindVdp) {
+    VdpField<R> F;
+    F.load(a, i, 2);
+    F(y, f);
+  } else {
+    LinearField<R> F;
+    F.load(a, i, a.dim[i]);
+    F(y, f);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kJointThreads) void joint_init_kernel(
+    AnalyticArgs<R> a) {
+  __shared__ double red[kJointThreads / 64];
+  __shared__ int32_t ref_s;
+  const int tid = threadIdx.x;
+  const long D = a.D;
+  if (tid == 0) ref_s = a.B;
+  __syncthreads();
+  for (int i = tid; i < a.B; i += kJointThreads) {
+    const bool ok = instance_ok(a, i);
+    a.st.status[i] = ok ? kRunning : kInvalid;
+    if (ok) atomicMin(&ref_s, i);
+  }
+  __syncthreads();
+  const int ref = ref_s;
+  double n_loc = 0.0, s0 = 0.0, s1 = 0.0;
+  for (int i = tid; i < a.B; i += kJointThreads) {
+    const bool member = ref < a.B && joint_member(a, i, ref);
+    const int dim = a.dim[i];
+    a.st.n_att[i] = a.st.n_acc[i] = a.st.n_rej[i] = a.st.n_fe[i] = 0;
+    a.st.cursor[i] = 0;
+    if (!member) {
+      a.st.status[i] = kInvalid;
+      a.st.t[i] = a.t0[i];
+      for (long q = 0; q < D; ++q) {
+        a.y_final[i * D + q] = quiet_nan<R>();
+        a.st.y[i * D + q] = quiet_nan<R>();
+      }
+      for (long e = 0; e < (long)a.E * D; ++e)
+        a.y_eval[i * a.E * D + e] = quiet_nan<R>();
+      continue;
+    }
+    R y[8], f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      y[q] = q < dim ? a.y0[i * D + q] : R(0);
+    joint_rhs(a, i, y, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q >= D) continue;
+      a.st.y[i * D + q] = q < dim ? y[q] : R(0);
+      a.st.k1[i * D + q] = q < dim ? f[q] : R(0);
+    }
+    for (int e = 0; e < a.E; ++e) {
+      const double te = a.t_eval[(long)i * a.E + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q >= D) continue;
+        a.y_eval[((long)i * a.E + e) * D + q] =
+            q < dim ? (te <= a.t0[i] ? y[q] : quiet_nan<R>()) : R(0);
+      }
+    }
+    n_loc += dim;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q >= dim) continue;
+      const R sc = R(a.atol[i]) + rabs(y[q]) * R(a.rtol[i]);
+      s0 += double((y[q] / sc) * (y[q] / sc));
+      s1 += double((f[q] / sc) * (f[q] / sc));
+    }
+  }
+  // Hairer's start step on the stacked vector (sums in the state precision
+  // for FP32, exactly as the independent solve forms them per instance)
+  const double n_tot = joint_sum(n_loc, red);
+  const double S0 = joint_sum(s0, red), S1 = joint_sum(s1, red);
+  JointState j{};
+  j.ref = ref;
+  j.n_total = int32_t(n_tot);
+  j.status = (ref < a.B) ? kRunning : kInvalid;
+  j.err_prev = j.err_prev2 = 1.0;
+  j.t = ref < a.B ? a.t0[ref] : 0.0;
+  j.t_end = ref < a.B ? a.t_end[ref] : 0.0;
+  j.cursor = 0;
+  if (ref < a.B)
+    while (j.cursor < a.E && a.t_eval[(long)ref * a.E + j.cursor] <= j.t)
+      ++j.cursor;
+  if (j.status == kRunning && j.t_end == j.t) {
+    j.status = kSuccess;
+  } else if (j.status == kRunning && a.h0 != nullptr) {
+    j.h = a.h0[ref];
+  } else if (j.status == kRunning) {
+    const double span = j.t_end - j.t;
+    const double d0 = sqrt(S0 / n_tot), d1 = sqrt(S1 / n_tot);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    h0 = fmin(h0, span);
+    double s2 = 0.0;
+    for (int i = tid; i < a.B; i += kJointThreads) {
+      if (!joint_member(a, i, ref)) continue;
+      const int dim = a.dim[i];
+      R y[8], f0[8], y1[8], f1[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        y[q] = q < dim ? a.st.y[i * D + q] : R(0);
+        f0[q] = q < dim ? a.st.k1[i * D + q] : R(0);
+        y1[q] = y[q] + R(h0) * f0[q];
+      }
+      joint_rhs(a, i, y1, f1);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q >= dim) continue;
+        const R sc = R(a.atol[i]) + rabs(y[q]) * R(a.rtol[i]);
+        const R d = (f1[q] - f0[q]) / sc;
+        s2 += double(d * d);
+      }
+    }
+    const double d2 = sqrt(joint_sum(s2, red) / n_tot) / h0;
+    const double h1 = (d1 <= 1e-15 && d2 <= 1e-15)
+                          ? fmax(1e-6, h0 * 1e-3)
+                          : pow(0.01 / fmax(d1, d2), 1.0 / 5.0);
+    j.h = fmin(fmin(100.0 * h0, h1), span);
+    j.probe = 1;
+  }
+  for (int i = tid; i < a.B; i += kJointThreads) {
+    if (a.st.status[i] == kInvalid) continue;
+    joint_write_stats(a, i, j);
+    if (j.status != kRunning) joint_finish(a, i, j);
+  }
+  if (tid == 0) *a.js = j;
+}
+
+template <typename R, class M>
+__global__ __launch_bounds__(kJointThreads) void joint_solve_kernel(
+    AnalyticArgs<R> a) {
+  __shared__ double red[kJointThreads / 64];
+  __shared__ JointState js;
+  __shared__ int32_t acc_s, cur_new;
+  __shared__ double tnew_s, fac_s;
+  const int tid = threadIdx.x;
+  const long B = a.B, D = a.D;
+  if (tid == 0) js = *a.js;
+  __syncthreads();
+  const int ref = js.ref;
+  const Ctrl& c = a.ctrl;
+  for (int it = 0; it < a.budget && js.status == kRunning; ++it) {
+    if (js.n_att >= c.max_steps) {
+      __syncthreads();
+      if (tid == 0) js.status = kMaxSteps;
+      __syncthreads();
+      break;
+    }
+    const bool last = js.t + js.h >= js.t_end;
+    const R hs = last ? R(js.t_end - js.t) : R(js.h);
+    double part = 0.0;
+    for (int i = tid; i < B; i += kJointThreads) {
+      if (a.st.status[i] == kInvalid) continue;
+      part += double(a.kind[i] == kKindVdp
+                         ? joint_stages<R, M, VdpField<R>>(a, i, js.t, hs)
+                         : joint_stages<R, M, LinearField<R>>(a, i, js.t, hs));
+    }
+    const double acc = joint_sum(part, red);
+    __syncthreads();
+    if (tid == 0) {
+      const double err = sqrt(acc / double(js.n_total));
+      const bool accept = err < 1.0;
+      double fac;
+      if (!__builtin_isfinite(err)) {
+        fac = c.fac_min;
+      } else if (accept) {
+        if (err == 0.0) {
+          fac = c.fac_max;
+        } else {
+          fac = c.safety * pow(err, -c.beta1) * pow(js.err_prev, c.beta2) *
+                pow(js.err_prev2, c.beta3);
+          fac = fac < c.fac_min ? c.fac_min : (fac > c.fac_max ? c.fac_max : fac);
+        }
+        if (js.prev_rej) fac = fmin(1.0, fac);
+      } else {
+        fac = fmax(c.fac_min, c.safety * pow(err, -1.0 / 5.0));
+      }
+      js.n_att += 1;
+      acc_s = accept;
+      int cur = js.cursor;
+      if (accept) {
+        const double tnew = last ? js.t_end : js.t + double(hs);
+        while (cur < a.E && a.t_eval[(long)ref * a.E + cur] <= tnew) ++cur;
+        tnew_s = tnew;
+        js.err_prev2 = js.err_prev;
+        js.err_prev = fmax(err, 1e-4);
+        js.n_acc += 1;
+        js.prev_rej = 0;
+        if (last) js.status = kSuccess;
+      } else {
+        tnew_s = js.t;
+        js.n_rej += 1;
+        js.prev_rej = 1;
+      }
+      cur_new = cur;
+      fac_s = fac;
+    }
+    __syncthreads();
+    if (acc_s) {  // dense outputs in (t, t_new], then y <- Y7, k1 <- k7
+      for (int i = tid; i < B; i += kJointThreads) {
+        if (a.st.status[i] == kInvalid) continue;
+        const int dim = a.dim[i];
+        for (int e = js.cursor; e < cur_new; ++e) {
+          const R th = R((a.t_eval[(long)ref * a.E + e] - js.t) / double(hs));
+          R w[7];
+#pragma unroll
+          for (int q = 0; q < 7; ++q)
+            w[q] = th * (R(M::P[q][0]) +
+                         th * (R(M::P[q][1]) +
+                               th * (R(M::P[q][2]) + th * R(M::P[q][3]))));
+          for (int q = 0; q < dim; ++q) {
+            R s2 = w[0] * a.st.k1[i * D + q];
+            for (int st = 1; st < 7; ++st)
+              s2 += w[st] * a.jK[((st - 1) * B + i) * D + q];
+            a.y_eval[((long)i * a.E + e) * D + q] = a.st.y[i * D + q] + hs * s2;
+          }
+        }
+        for (int q = 0; q < dim; ++q) {
+          a.st.y[i * D + q] = a.jY[i * D + q];
+          a.st.k1[i * D + q] = a.jK[(5 * B + i) * D + q];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      if (acc_s) {
+        js.t = tnew_s;
+        js.cursor = cur_new;
+      }
+      js.h = double(hs * R(fac_s));  // in the state precision
+      if (js.status == kRunning &&
+          !(js.h > 16.0 * DBL_EPSILON * fabs(js.t)))
+        js.status = kDtUnderflow;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int i = tid; i < B; i += kJointThreads) {
+    if (a.st.status[i] == kInvalid) continue;
+    joint_write_stats(a, i, js);
+    if (js.status != kRunning) joint_finish(a, i, js);
+  }
+  if (tid == 0) *a.js = js;
+}
+
 template <typename R>
 hipError_t launch_analytic_init(const AnalyticArgs<R>& a, int, hipStream_t s) {
   const int block = 256;
@@ -609,6 +972,37 @@ hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_joint_init(const AnalyticArgs<R>& a, int, hipStream_t s) {
+  if (a.js == nullptr || a.jK == nullptr || a.jY == nullptr)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(joint_init_kernel<R>, dim3(1), dim3(kJointThreads), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_joint_solve(const AnalyticArgs<R>& a, int method,
+                              hipStream_t s) {
+  if (a.js == nullptr || a.jK == nullptr || a.jY == nullptr)
+    return hipErrorInvalidValue;
+  if (method == 1)
+    hipLaunchKernelGGL((joint_solve_kernel<R, Tsit5>), dim3(1),
+                       dim3(kJointThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((joint_solve_kernel<R, Dopri5>), dim3(1),
+                       dim3(kJointThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_joint_init<double>(const AnalyticArgs<double>&,
+                                              int, hipStream_t);
+template hipError_t launch_joint_init<float>(const AnalyticArgs<float>&, int,
+                                             hipStream_t);
+template hipError_t launch_joint_solve<double>(const AnalyticArgs<double>&,
+                                               int, hipStream_t);
+template hipError_t launch_joint_solve<float>(const AnalyticArgs<float>&, int,
+                                              hipStream_t);
 template hipError_t launch_analytic_init<double>(const AnalyticArgs<double>&,
                                                  int, hipStream_t);
 template hipError_t launch_analytic_init<float>(const AnalyticArgs<float>&,

@@ -125,6 +125,11 @@ std::string check_config(const bode_config* c) {
       !std::isfinite(c->safety))
     return "controller needs safety > 0, 0 < fac_min <= 1 <= fac_max, "
            "finite beta1 >= 0, finite beta2 and beta3";
+  if (c->joint != 0 && c->joint != 1) return "joint must be 0 or 1";
+  if (c->joint && (c->rhs != BODE_RHS_ANALYTIC || c->record_cap != 0 ||
+                   c->keep_dense != 0))
+    return "joint mode is built for analytic fields without record_cap or "
+           "keep_dense";
   if (c->record_cap < 0) return "record_cap must be >= 0";
   if (c->ckpt_every < 0) return "ckpt_every must be >= 0";
   if (c->ckpt_every > 0 && c->record_cap < 1)
@@ -166,7 +171,17 @@ size_t layout_analytic(const bode_config& c, void* base,
     dk.y_prev = L.take<R>(B * D);
     dk.q = L.take<R>(4 * B * D);
   }
+  bode::JointState* js = nullptr;
+  R *jK = nullptr, *jY = nullptr;
+  if (c.joint) {
+    js = L.take<bode::JointState>(1);
+    jK = L.take<R>(6 * B * D);
+    jY = L.take<R>(B * D);
+  }
   if (a) {
+    a->js = js;
+    a->jK = jK;
+    a->jY = jY;
     a->st = st;
     a->list = list;
     a->counts = cnt;
@@ -227,6 +242,10 @@ void fill_analytic_args(bode_solver* s, bode::AnalyticArgs<R>* a) {
 template <typename R>
 int run_analytic(bode_solver* s, bode::AnalyticArgs<R>& a, int budget) {
   a.budget = budget;
+  if (s->cfg.joint) {
+    HIP_TRY(bode::launch_joint_solve<R>(a, s->cfg.method, s->stream));
+    return BODE_OK;
+  }
   HIP_TRY(bode::launch_fill_i32(s->counts + 2, 2, 0, s->stream));
   HIP_TRY(hipEventRecord(s->ev_fork, s->stream));
   HIP_TRY(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
@@ -339,14 +358,20 @@ int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
         fill_analytic_args<double>(s, &s->ad);
         e = bode::launch_fill_i32(s->counts, 8, 0, s->stream);
         if (e == hipSuccess)
-          e = bode::launch_analytic_init<double>(s->ad, cfg->method, s->stream);
+          e = cfg->joint ? bode::launch_joint_init<double>(s->ad, cfg->method,
+                                                   s->stream)
+                         : bode::launch_analytic_init<double>(s->ad, cfg->method,
+                                                      s->stream);
       } else {
         layout_analytic<float>(*cfg, workspace, &s->af, &s->counts,
                                &s->n_running_dev);
         fill_analytic_args<float>(s, &s->af);
         e = bode::launch_fill_i32(s->counts, 8, 0, s->stream);
         if (e == hipSuccess)
-          e = bode::launch_analytic_init<float>(s->af, cfg->method, s->stream);
+          e = cfg->joint ? bode::launch_joint_init<float>(s->af, cfg->method,
+                                                   s->stream)
+                         : bode::launch_analytic_init<float>(s->af, cfg->method,
+                                                      s->stream);
       }
       if (e != hipSuccess) {
         std::string m = std::string("init launch: ") + hipGetErrorString(e);
