@@ -51,19 +51,19 @@ __global__ void fvec_kernel(float* f, const float* W1, const float* b1,
   }
 }
 
-template <class Op, int NTW, bool CNF>
-__global__ __launch_bounds__(256) void field_mfma_kernel(MfmaArgs a) {
+template <class Op, int NTW, bool CNF, int WV>
+__global__ __launch_bounds__(64 * WV) void field_mfma_kernel(MfmaArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  field_tile<Op, NTW, CNF>(a, blockIdx.x * (CNF ? 8 : 16), smem_raw);
+  field_tile<Op, NTW, CNF, WV>(a, blockIdx.x * (CNF ? 8 : 16), smem_raw);
 }
 
-template <class Op, int NTW, bool CNF>
+template <class Op, int NTW, bool CNF, int WV>
 hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
-  const size_t sm = mfma_smem<Op, NTW, CNF>(a.din);
+  const size_t sm = mfma_smem<Op, NTW, CNF, WV>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((field_mfma_kernel<Op, NTW, CNF>),
-                     dim3((a.B + PR - 1) / PR), dim3(256), sm, s, a);
+  hipLaunchKernelGGL((field_mfma_kernel<Op, NTW, CNF, WV>),
+                     dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
   return hipGetLastError();
 }
 
@@ -76,11 +76,12 @@ hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
 // (plus the CNF's second-order term), S1 = G2 W2^T, G1 = tanh'(p1) S1,
 // mu = G1 W1^T.  For the CNF, gbar's tangent rows hold -kappa_l eps, the
 // cotangent of the tangent output.
-template <class Op, int NTW, bool CNF>
-__global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
+template <class Op, int NTW, bool CNF, int WV>
+__global__ __launch_bounds__(64 * WV) void vjp_mfma_kernel(MfmaVjpArgs a) {
   typedef typename Op::A A;
   typedef typename Op::W W;
-  constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 64, SA = H + Op::kPad;
+  constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 16 * WV,
+                SA = H + Op::kPad;
   const int din = a.din, D = a.D, B = a.B;
   const Dims dm = dims(din, H);
   const DimsT dt = dims_t(din, H);
@@ -256,19 +257,19 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
     __syncthreads();
   }
 
-  // mu = G1 W1^T (primal rows); column tiles nb = wave, wave + 4, ...
+  // mu = G1 W1^T (primal rows); column tiles nb = wave, wave + WV, ...
   {
-    const int ntiles = (dt.nn1 - wave + 3) / 4;
+    const int ntiles = (dt.nn1 - wave + WV - 1) / WV;
     f32x4 acc[1][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
       Op::template gemm<1, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
-                 4, ntiles, lane);
+                 WV, ntiles, lane);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t >= ntiles) continue;
-      const int n = (wave + 4 * t) * 16 + col;
+      const int n = (wave + WV * t) * 16 + col;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = rq + i;
@@ -296,13 +297,13 @@ __global__ __launch_bounds__(256) void vjp_mfma_kernel(MfmaVjpArgs a) {
   }
 }
 
-template <class Op, int NTW, bool CNF>
+template <class Op, int NTW, bool CNF, int WV>
 hipError_t launch_vjp_t(const MfmaVjpArgs& a, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
-  const size_t sm = mfma_smem<Op, NTW, CNF>(a.din);
+  const size_t sm = mfma_smem<Op, NTW, CNF, WV>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF>), dim3((a.B + PR - 1) / PR),
-                     dim3(256), sm, s, a);
+  hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF, WV>),
+                     dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
   return hipGetLastError();
 }
 
@@ -331,23 +332,25 @@ hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
   return hipGetLastError();
 }
 
+// Hidden width -> (column tiles per wavefront, wavefronts): 8 wavefronts
+// from H = 128 up, so a tile's layers run on two wavefronts per SIMD.
 template <class Op, bool CNF>
 hipError_t field_h(const MfmaArgs& a, hipStream_t s) {
   switch (a.H) {
-    case 512: return launch_t<Op, 8, CNF>(a, s);
-    case 256: return launch_t<Op, 4, CNF>(a, s);
-    case 128: return launch_t<Op, 2, CNF>(a, s);
-    default: return launch_t<Op, 1, CNF>(a, s);
+    case 512: return launch_t<Op, 4, CNF, 8>(a, s);
+    case 256: return launch_t<Op, 2, CNF, 8>(a, s);
+    case 128: return launch_t<Op, 1, CNF, 8>(a, s);
+    default: return launch_t<Op, 1, CNF, 4>(a, s);
   }
 }
 
 template <class Op, bool CNF>
 hipError_t vjp_h(const MfmaVjpArgs& a, hipStream_t s) {
   switch (a.H) {
-    case 512: return launch_vjp_t<Op, 8, CNF>(a, s);
-    case 256: return launch_vjp_t<Op, 4, CNF>(a, s);
-    case 128: return launch_vjp_t<Op, 2, CNF>(a, s);
-    default: return launch_vjp_t<Op, 1, CNF>(a, s);
+    case 512: return launch_vjp_t<Op, 4, CNF, 8>(a, s);
+    case 256: return launch_vjp_t<Op, 2, CNF, 8>(a, s);
+    case 128: return launch_vjp_t<Op, 1, CNF, 8>(a, s);
+    default: return launch_vjp_t<Op, 1, CNF, 4>(a, s);
   }
 }
 

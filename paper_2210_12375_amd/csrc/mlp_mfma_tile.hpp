@@ -228,9 +228,9 @@ struct F32 {
 
 // The field for the 16-row tile starting at instance r0 (MLP: 16
 // instances; CNF: 8 instances and their 8 tangent rows), by a workgroup of
-// 4 wavefronts; NTW = H / 64 column tiles per wavefront in the hidden
-// layers.  smem_raw: mfma_smem<Op, NTW, CNF>(din) bytes of LDS.
-template <class Op, int NTW, bool CNF>
+// WV wavefronts; NTW = H / (16 WV) column tiles per wavefront in the hidden
+// layers.  smem_raw: mfma_smem<Op, NTW, CNF, WV>(din) bytes of LDS.
+template <class Op, int NTW, bool CNF, int WV>
 __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
                                            unsigned char* smem_raw) {
   constexpr int MT = 1;
@@ -238,7 +238,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   typedef typename Op::W W;
   constexpr int RT = 16 * MT;
   constexpr int PR = CNF ? 8 : RT;  // instances per workgroup
-  constexpr int H = NTW * 64;
+  constexpr int H = NTW * 16 * WV;
   constexpr int SA = H + Op::kPad;  // LDS row stride (bank spread)
   const int din = a.din, D = a.D, B = a.B;
   const Dims dm = dims(din, H);
@@ -334,9 +334,9 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
     __syncthreads();
   }
 
-  // output layer: column tiles nb = wave, wave + 4, ...
+  // output layer: column tiles nb = wave, wave + WV, ...
   {
-    const int ntiles = (dm.nn3 - wave + 3) / 4;
+    const int ntiles = (dm.nn3 - wave + WV - 1) / WV;
     f32x4 acc[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -344,13 +344,13 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
       for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
       Op::template gemm<MT, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off3, dm.nk3, dm.nn3, wave,
-                  4, ntiles, lane);
+                  WV, ntiles, lane);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         if (t >= ntiles) continue;
-        const int nb = wave + 4 * t;
+        const int nb = wave + WV * t;
         const int n = nb * 16 + col;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -383,10 +383,10 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   }
 }
 
-template <class Op, int NTW, bool CNF>
+template <class Op, int NTW, bool CNF, int WV>
 __host__ __device__ inline size_t mfma_smem(int din) {
   constexpr int MT = 1;
-  constexpr int RT = 16 * MT, PR = CNF ? 8 : RT, H = NTW * 64;
+  constexpr int RT = 16 * MT, PR = CNF ? 8 : RT, H = NTW * 16 * WV;
   const Dims dm = dims(din, H);
   return sizeof(typename Op::A) * Op::kPlanes *
              ((size_t)RT * (dm.K1 + Op::kPad) + RT * (H + Op::kPad)) +

@@ -601,9 +601,9 @@ struct FusedArgs {
   int budget;      // attempts per instance
 };
 
-template <class Op, int NTW, bool CNF, class M>
-__global__ __launch_bounds__(256) void solve_fused_kernel(Mod<float> m,
-                                                          FusedArgs f) {
+template <class Op, int NTW, bool CNF, int WV, class M>
+__global__ __launch_bounds__(64 * WV) void solve_fused_kernel(Mod<float> m,
+                                                              FusedArgs f) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int PR = CNF ? 8 : 16;
   const int r0 = blockIdx.x * PR;
@@ -619,31 +619,31 @@ __global__ __launch_bounds__(256) void solve_fused_kernel(Mod<float> m,
     __syncthreads();
     if (!active) break;
     for (int s = 0; s < 6; ++s) {
-      mtile::field_tile<Op, NTW, CNF>(f.st[s], r0, smem_raw);
+      mtile::field_tile<Op, NTW, CNF, WV>(f.st[s], r0, smem_raw);
       __syncthreads();
     }
-    for (int r = wave; r < PR; r += 4)
+    for (int r = wave; r < PR; r += WV)
       commit_row<float, M, false>(m, r0 + r, lane);
   }
 }
 
-template <class Op, int NTW, bool CNF, class M>
+template <class Op, int NTW, bool CNF, int WV, class M>
 hipError_t fused_t(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
-  const size_t sm = mtile::mfma_smem<Op, NTW, CNF>(m.d_in);
+  const size_t sm = mtile::mfma_smem<Op, NTW, CNF, WV>(m.d_in);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((solve_fused_kernel<Op, NTW, CNF, M>),
-                     dim3((m.B + PR - 1) / PR), dim3(256), sm, s, m, f);
+  hipLaunchKernelGGL((solve_fused_kernel<Op, NTW, CNF, WV, M>),
+                     dim3((m.B + PR - 1) / PR), dim3(64 * WV), sm, s, m, f);
   return hipGetLastError();
 }
 
 template <class Op, bool CNF, class M>
 hipError_t fused_h(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
   switch (m.H) {
-    case 512: return fused_t<Op, 8, CNF, M>(m, f, s);
-    case 256: return fused_t<Op, 4, CNF, M>(m, f, s);
-    case 128: return fused_t<Op, 2, CNF, M>(m, f, s);
-    default: return fused_t<Op, 1, CNF, M>(m, f, s);
+    case 512: return fused_t<Op, 4, CNF, 8, M>(m, f, s);
+    case 256: return fused_t<Op, 2, CNF, 8, M>(m, f, s);
+    case 128: return fused_t<Op, 1, CNF, 8, M>(m, f, s);
+    default: return fused_t<Op, 1, CNF, 4, M>(m, f, s);
   }
 }
 
