@@ -1596,6 +1596,92 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
       }
 }
 
+// Large layers (both sides >= 256, long tapes): 256 x 256 tiles of C over
+// 8 wavefronts (4 x 2, each 64 x 128 = 4 x 8 MFMA tiles), so each tape row
+// is read by only M/256 + N/256 workgroups.  C rows [0, M) are the weight
+// rows of the layer; its bias row (input feature M, the last of the ldin
+// columns) is summed by the first row of tiles from the same staged
+// cotangent block, on plain FMAs.
+__global__ __launch_bounds__(512) void grad_gemm_big(
+    const float* Tin, int ldin, const float* Tg, long K, int M, int N, int S,
+    float* slots, long P, long off) {
+  constexpr int TT = 256, TK = 16, LA = TT + 16;
+  constexpr int NL = TK * TT / 512;  // loads per thread per operand
+  __shared__ float As[TK * LA];
+  __shared__ float Bs[TK * LA];
+  __shared__ float Bias[TK];
+  const int tiles_n = (N + TT - 1) / TT;
+  const int tile = blockIdx.x / S, split = blockIdx.x % S;
+  const int m0 = (tile / tiles_n) * TT, n0 = (tile % tiles_n) * TT;
+  const bool brow = m0 == 0;
+  const long kc = ((K + S - 1) / S + TK - 1) / TK * TK;
+  const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4_t acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  float ra[NL], rb[NL], rbias = 0.f;
+  auto fetch = [&](long kk) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + 512 * q, kl = e / TT, c = e % TT;
+      const long k = kk + kl;
+      ra[q] = (m0 + c < M && k < k1) ? Tin[k * ldin + m0 + c] : 0.f;
+      rb[q] = (n0 + c < N && k < k1) ? Tg[k * N + n0 + c] : 0.f;
+    }
+    if (brow && tid < TK)
+      rbias = kk + tid < k1 ? Tin[(kk + tid) * ldin + M] : 0.f;
+  };
+  if (k0 < k1) fetch(k0);
+  for (long kk = k0; kk < k1; kk += TK) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + 512 * q;
+      As[(e / TT) * LA + e % TT] = ra[q];
+      Bs[(e / TT) * LA + e % TT] = rb[q];
+    }
+    if (brow && tid < TK) Bias[tid] = rbias;
+    __syncthreads();
+    if (kk + TK < k1) fetch(kk + TK);
+#pragma unroll
+    for (int k4 = 0; k4 < TK; k4 += 4) {
+      float a[4], b[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[(k4 + lk) * LA + wm + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[j] = Bs[(k4 + lk) * LA + wn + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc[i][j] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (brow && tid < TT) {
+#pragma unroll
+      for (int kl = 0; kl < TK; ++kl) bacc += Bias[kl] * Bs[kl * LA + tid];
+    }
+    __syncthreads();
+  }
+  float* slot = slots + (long)split * P + off;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + i * 16 + lk * 4 + v;
+        const int n = n0 + wn + j * 16 + lr;
+        if (m < M && n < N) slot[(long)m * N + n] += acc[i][j][v];
+      }
+  if (brow && tid < TT && n0 + tid < N) slot[(long)M * N + n0 + tid] += bacc;
+}
+
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int S, R* slots, long P, long off, hipStream_t s) {
@@ -1613,6 +1699,18 @@ hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
   if (splits > S) splits = S;
   const dim3 g(tiles * splits), blk(256);
   if constexpr (std::is_same<R, float>::value) {
+    if (M - 1 >= 256 && N >= 256 && K >= 65536) {
+      // weight rows on 256 x 256 tiles; the bias row is the last input
+      // feature and rides with the first row of tiles
+      const int Mw = M - 1;
+      const int tb = ((Mw + 255) / 256) * ((N + 255) / 256);
+      int sb = (1024 + tb - 1) / tb;
+      if (sb > by_k) sb = (int)by_k;
+      if (sb > S) sb = S;
+      hipLaunchKernelGGL(grad_gemm_big, dim3(tb * sb), dim3(512), 0, s, Tin,
+                         M, Tg, K, Mw, N, sb, slots, P, off);
+      return hipGetLastError();
+    }
     if (tm == 32)
       hipLaunchKernelGGL((grad_gemm_mfma<1, 4>), g, blk, 0, s, Tin, Tg, K, M,
                          N, splits, slots, P, off);

@@ -196,3 +196,45 @@ def test_autograd_function_matches_oracle():
     assert rel_l2(y0.grad.cpu().numpy(), dy0) <= 1e-8
     got = np.concatenate([params[k].grad.cpu().numpy().ravel() for k in AP])
     assert rel_l2(got, dth) <= 1e-8
+
+
+@pytest.mark.parametrize("precision,d,hidden,cnf,reps", [
+    # CNF hidden layer 512 x 512 (+ bias row), 67,200 tape rows: the
+    # 256 x 256 gradient tiles, 2 x 2 of them
+    ("bf16", 16, 512, True, 400),
+    # MLP hidden layer 384 x 384 on FMA fields, 67,200 tape rows: ragged
+    # 256 x 256 gradient tiles
+    ("fp32", 32, 384, False, 800),
+])
+def test_gradient_of_a_replicated_batch(precision, d, hidden, cnf, reps):
+    """Long tapes at a size the oracle cannot take whole: 12 distinct
+    instances repeated reps times.  Each copy solves and differentiates the
+    same problem, so every copy's dy0 equals the oracle's dy0 of its
+    original, and d theta, a sum over instances, is reps times the oracle's
+    d theta of the 12."""
+    flush(f"replicated adjoint {precision} d={d} H={hidden} cnf={cnf} "
+          f"reps={reps}")
+    base = (W.cnf_density(B=12, d=d, hidden=hidden) if cnf
+            else W.neural_ode_fit(B=12, d=d, hidden=hidden))
+    rhs = bd.RHS_CNF if cnf else bd.RHS_MLP
+    idx = np.tile(np.arange(12), reps)
+    p = W.subset(base, idx)
+    g_eval0, g_final0 = cotangents(base)
+    g_eval = None if g_eval0 is None else g_eval0[idx]
+    g = gpu_grad(p, "dopri5", precision, rhs, 2, g_eval, g_final0[idx])
+    assert np.all(g["status"] == bd.SUCCESS)
+    n12 = g["n"][:12]
+    for r in range(1, reps):  # identical inputs take identical steps
+        assert np.array_equal(g["n"][12 * r:12 * r + 12], n12)
+    h12 = g["h"][:12]
+    for i in range(12):
+        k = int(n12[i])
+        assert np.array_equal(g["h"][12 + i, :k], h12[i, :k])
+    (dy0, dth), _ = oracle_grad(as_float_inputs(base),
+                                dict(h=h12, n=n12), "dopri5", g_eval0,
+                                g_final0)
+    e0 = rel_l2(g["dy0"], np.tile(dy0, (reps, 1)))
+    e1 = rel_l2(g["dth"], reps * dth)
+    flush(f"  dy0 {e0:.2e} dtheta {e1:.2e}")
+    tol = 1e-4 if precision == "fp32" else 1e-2
+    assert e0 <= tol and e1 <= tol, (e0, e1)
