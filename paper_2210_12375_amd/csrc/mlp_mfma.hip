@@ -333,11 +333,15 @@ hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
 }
 
 // Hidden width -> (column tiles per wavefront, wavefronts): 8 wavefronts
-// from H = 128 up, so a tile's layers run on two wavefronts per SIMD.
+// from H = 128 up, so a tile's layers run on two wavefronts per SIMD; the
+// CNF field at H = 512 keeps 4 (8 column tiles each), which measured faster
+// for its 8 primal + 8 tangent rows (62 vs 75 us per stage at 8192
+// instances), while its VJP is faster on 8.
 template <class Op, bool CNF>
 hipError_t field_h(const MfmaArgs& a, hipStream_t s) {
   switch (a.H) {
-    case 512: return launch_t<Op, 4, CNF, 8>(a, s);
+    case 512:
+      return CNF ? launch_t<Op, 8, CNF, 4>(a, s) : launch_t<Op, 4, CNF, 8>(a, s);
     case 256: return launch_t<Op, 2, CNF, 8>(a, s);
     case 128: return launch_t<Op, 1, CNF, 8>(a, s);
     default: return launch_t<Op, 1, CNF, 4>(a, s);
