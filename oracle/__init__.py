@@ -3,5 +3,6 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 benchmark's CPU-baseline leg, never by the product package.
 """
-from .oracle import (accepted_steps, adjoint, dense_weights,  # noqa: F401
-                     initial_step, rhs, solve, solve_joint, tableau)
+from .oracle import (accepted_steps, adjoint, cadjoint,  # noqa: F401
+                     dense_weights, initial_step, rhs, solve, solve_joint,
+                     tableau)

@@ -173,6 +173,17 @@ static void vjp_cnf(const orc_problem* P, int32_t inst, double t,
 }
 
 static void vjp(const orc_problem* P, int32_t i, double t, const double* y,
+                const double* kap, double* mu, grads G);
+
+void orc_vjp(const orc_problem* P, int32_t i, double t, const double* y,
+             const double* kap, double* mu, double* dtheta) {
+  double dummy[1] = {0.0};
+  vjp(P, i, t, y, kap, mu, split(P, P->W1 ? dtheta : dummy));
+}
+
+long orc_n_params(const orc_problem* P) { return P->W1 ? n_params(P) : 0; }
+
+static void vjp(const orc_problem* P, int32_t i, double t, const double* y,
                 const double* kap, double* mu, grads G) {
   const int n = P->dim[i];
   switch (P->kind[i]) {

@@ -8,7 +8,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["tableau.c", "rhs.c", "solve.c", "joint.c", "adjoint.c"]
+SOURCES = ["tableau.c", "rhs.c", "solve.c", "joint.c", "adjoint.c",
+           "cadjoint.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 # The same source with every a*b+c contracted into a fused multiply-add.  It
 # is not a second oracle: the tests use it only to find instances whose step

@@ -134,6 +134,15 @@ int orc_adjoint(const orc_problem* P, const orc_options* O,
                 const double* g_eval, const double* g_final, double* dy0,
                 double* dtheta);
 
+/* mu = J_f(t, y)^T kap for instance i (mu, kap: [dim]); for MLP / CNF
+ * right-hand sides (df/dtheta)^T kap is added into dtheta (layout as
+ * orc_adjoint's; may be NULL for the analytic fields).                     */
+void orc_vjp(const orc_problem* P, int32_t i, double t, const double* y,
+             const double* kap, double* mu, double* dtheta);
+
+/* Number of MLP parameters (0 without an MLP). */
+long orc_n_params(const orc_problem* P);
+
 /* Tableau export for the tests: c[7], a[7*7] (row-major), b[7], bhat[7].   */
 void orc_tableau(int32_t method, double* c, double* a, double* b,
                  double* bhat);
@@ -155,6 +164,24 @@ int orc_instance_valid(const orc_problem* P, int32_t i);
  * options' replay and recording fields are not used.                        */
 int orc_solve_joint(const orc_problem* P, const orc_options* O,
                     double* y_eval, double* y_final, int32_t* stats);
+
+/* Continuous adjoint (appendix A, the adjoint-equation training of the
+ * CNF): the augmented system y' = f, a' = -(df/dy)^T a, g' = -(df/dtheta)^T a
+ * integrated adaptively from t_end back to t0 (cadjoint.c), per instance
+ * (joint = 0: every instance its own (y, a, g), b (f + p) variables) or
+ * jointly (joint = 1: the members' y and a stacked with one shared g, one
+ * step size; members are the instances with fwd_status SUCCESS and the first
+ * such instance's t0, t_end and t_eval).  y_final [B, D] and fwd_status [B]
+ * come from the forward solve; g_eval [B, E, D] (may be NULL when E = 0) and
+ * g_final [B, D] are the output cotangents.  Outputs dy0 [B, D] (NaN for
+ * instances not differentiated), dtheta [p] (MLP / CNF; the sum over
+ * instances) and stats [5, B] of the backward solve (attempted, accepted,
+ * rejected, augmented evaluations, status; INVALID for instances not
+ * differentiated).  Returns 0, or -1 for invalid arguments.                */
+int orc_cadjoint(const orc_problem* P, const orc_options* O, int32_t joint,
+                 const double* y_final, const int32_t* fwd_status,
+                 const double* g_eval, const double* g_final, double* dy0,
+                 double* dtheta, int32_t* stats);
 
 #ifdef __cplusplus
 }

@@ -81,6 +81,10 @@ def _load(variant=None):
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint.argtypes = [C.POINTER(_Problem), C.POINTER(_Options),
                                     _dp, _ip, C.c_int32, _dp, _dp, _dp, _dp]
+        lib.orc_cadjoint.restype = C.c_int
+        lib.orc_cadjoint.argtypes = [C.POINTER(_Problem), C.POINTER(_Options),
+                                     C.c_int32, _dp, _ip, _dp, _dp, _dp, _dp,
+                                     _ip]
         lib.orc_rhs.restype = None
         lib.orc_rhs.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_double,
                                 _dp, _dp]
@@ -258,6 +262,44 @@ def adjoint(problem, h_steps, n_steps, g_eval, g_final, method="dopri5",
     if rc != 0:
         raise ValueError("oracle adjoint rejected its arguments")
     return dy0, dtheta
+
+
+def cadjoint(problem, y_final, fwd_status, g_eval, g_final, joint=False,
+             method="dopri5", beta1=PI_CONTROLLER["beta1"],
+             beta2=PI_CONTROLLER["beta2"], beta3=0.0, safety=0.9,
+             fac_min=0.2, fac_max=10.0, max_steps=100000, n_threads=0):
+    """Continuous adjoint (appendix A): the augmented system integrated from
+    t_end back to t0, per instance (b (f + p) variables) or joint (one
+    shared parameter adjoint and step size).  y_final and fwd_status come
+    from the forward solve.
+
+    Returns dict(dy0 [B, D], dtheta [p] or None, and the backward solve's
+    n_attempted, n_accepted, n_rejected, n_feval, status)."""
+    lib = _load()
+    m = _Marshalled(problem)
+    o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
+                 n_threads)
+    o.beta3 = beta3
+    y_final = _f64(y_final)
+    fwd_status = np.ascontiguousarray(fwd_status, dtype=np.int32)
+    g_eval = _f64(np.zeros((m.B, m.E, m.D)) if g_eval is None else g_eval)
+    g_final = _f64(g_final)
+    dy0 = np.zeros((m.B, m.D))
+    dtheta = None
+    mlp = problem.get("mlp")
+    if mlp is not None:
+        dtheta = np.zeros(sum(np.asarray(mlp[k]).size
+                              for k in ("W1", "b1", "W2", "b2", "W3", "b3")))
+    stats = np.zeros((5, m.B), dtype=np.int32)
+    rc = lib.orc_cadjoint(C.byref(m.s), C.byref(o), int(bool(joint)),
+                          _ptr(y_final), _ptr(fwd_status, _ip), _ptr(g_eval),
+                          _ptr(g_final), _ptr(dy0), _ptr(dtheta),
+                          _ptr(stats, _ip))
+    if rc != 0:
+        raise ValueError("oracle continuous adjoint rejected its arguments")
+    return dict(dy0=dy0, dtheta=dtheta, n_attempted=stats[0],
+                n_accepted=stats[1], n_rejected=stats[2], n_feval=stats[3],
+                status=stats[4])
 
 
 def rhs(problem, i, t, y):
