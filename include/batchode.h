@@ -189,6 +189,40 @@ int solver_eval(bode_solver* s, const double* t_query, void* y_out,
 int solver_backward(bode_solver* s, const void* g_y_eval, const void* g_y_final,
                     void* dy0, void* dtheta);
 
+/* Continuous adjoint (appendix A: the CNF is trained through the adjoint
+ * equation).  After a completed solve of an MLP or CNF field, the augmented
+ * system y' = f, a' = -(df/dy)^T a, g' = -(df/dtheta)^T a is integrated
+ * adaptively from t_end back to t0 with the solve's method, controller,
+ * tolerances and max_steps, starting from y_final, a = the cotangent of
+ * y(t_end) and g = 0; the solve stops at every evaluation time inside
+ * (t0, t_end) to add that output's cotangent to a.  joint = 0: every
+ * instance integrates its own (y_i, a_i, g_i), 2 D + P variables with its
+ * own steps and error norm (the paper's b (f + p) system); joint = 1: the
+ * members (instances whose solve succeeded and that share the first such
+ * instance's t0, t_end and t_eval) are stacked with one shared g into one
+ * system with one step size (the b f + p system).  Each component is scaled
+ * by atol + rtol max(|z_n|, |z_n+1|) with its instance's tolerances (the
+ * shared g with the first member's); the start step is Hairer's rule on the
+ * augmented state.
+ * g_y_eval [B, E, D] (may be NULL when E = 0) and g_y_final [B, D] are
+ * state-typed device arrays.  Outputs (device): dy0 [B, D] = a(t0) plus the
+ * cotangents at t0 (NaN for instances not differentiated), dtheta [P] = the
+ * sum of the g_i (per instance) or the shared g, in solver_backward's
+ * layout, and, if stats is not NULL, int32 [5, B] of the backward solve:
+ * attempted, accepted, rejected steps, augmented evaluations (1 + probe + 6
+ * per attempt + 1 per evaluation-time stop) and status (BODE_INVALID for
+ * instances not differentiated).  workspace: device memory of at least
+ * solver_cadjoint_workspace_bytes(s, joint) bytes, owned by the caller;
+ * per instance it holds two [B, P] copies of the parameter adjoints.
+ * Synchronises the stream a few times per step.  Errors: BODE_EINVAL
+ * (missing argument, joint not 0/1, workspace too small), BODE_ESTATE (no
+ * completed solve), BODE_EUNSUPPORTED (analytic right-hand sides).        */
+size_t solver_cadjoint_workspace_bytes(const bode_solver* s, int32_t joint);
+int solver_cadjoint(bode_solver* s, int32_t joint, const void* g_y_eval,
+                    const void* g_y_final, void* workspace,
+                    size_t workspace_bytes, void* dy0, void* dtheta,
+                    int32_t* stats);
+
 /* Per-instance statistics (section 3: total and accepted steps are collected
  * by default), copied asynchronously into device int32 arrays [B] (any may
  * be NULL): attempted, accepted and rejected steps, right-hand-side

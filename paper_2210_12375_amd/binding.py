@@ -36,6 +36,7 @@ def pid_gains(k_i, k_p, k_d, order=5):
 
 EXPORTED = ["solver_workspace_size", "solver_init", "solver_step",
             "solver_solve", "solver_eval", "solver_backward",
+            "solver_cadjoint_workspace_bytes", "solver_cadjoint",
             "solver_get_stats", "solver_get_steps", "solver_autotune",
             "solver_destroy", "solver_last_error", "solver_tableau"]
 
@@ -94,6 +95,11 @@ def lib():
         L.solver_eval.argtypes = [vp, dp, vp, ip]
         L.solver_backward.restype = C.c_int
         L.solver_backward.argtypes = [vp, vp, vp, vp, vp]
+        L.solver_cadjoint_workspace_bytes.restype = C.c_size_t
+        L.solver_cadjoint_workspace_bytes.argtypes = [vp, C.c_int32]
+        L.solver_cadjoint.restype = C.c_int
+        L.solver_cadjoint.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_size_t,
+                                      vp, vp, vp]
         L.solver_get_stats.restype = C.c_int
         L.solver_get_stats.argtypes = [vp, ip, ip, ip, ip, ip]
         L.solver_get_steps.restype = C.c_int
@@ -170,6 +176,17 @@ def solver_eval(h, t_query_ptr, y_out_ptr, qstatus_ptr):
 def solver_backward(h, g_eval_ptr, g_final_ptr, dy0_ptr, dtheta_ptr):
     _check(lib().solver_backward(h, g_eval_ptr, g_final_ptr, dy0_ptr,
                                  dtheta_ptr), h)
+
+
+def solver_cadjoint_workspace_bytes(h, joint):
+    return int(lib().solver_cadjoint_workspace_bytes(h, int(joint)))
+
+
+def solver_cadjoint(h, joint, g_eval_ptr, g_final_ptr, ws_ptr, ws_bytes,
+                    dy0_ptr, dtheta_ptr, stats_ptr):
+    _check(lib().solver_cadjoint(h, int(joint), g_eval_ptr, g_final_ptr,
+                                 ws_ptr, ws_bytes, dy0_ptr, dtheta_ptr,
+                                 stats_ptr), h)
 
 
 def solver_get_stats(h, *ptrs):
@@ -326,6 +343,23 @@ class Solver:
                         None if g_eval is None else g_eval.data_ptr(),
                         g_final.data_ptr(), dy0.data_ptr(), dth.data_ptr())
         return dy0, dth
+
+    def cadjoint(self, g_eval, g_final, n_params, joint=False):
+        """Continuous adjoint of the completed solve; returns (dy0, dtheta,
+        stats [5, B]).  The workspace is allocated here for the call."""
+        torch = self.torch
+        dev = self.y_final.device
+        nb = solver_cadjoint_workspace_bytes(self.handle, joint)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dy0 = torch.empty_like(self.y_final)
+        dth = torch.empty(n_params, dtype=self.y_final.dtype, device=dev)
+        st = torch.empty((5, self.B), dtype=torch.int32, device=dev)
+        solver_cadjoint(self.handle, joint,
+                        None if g_eval is None else g_eval.data_ptr(),
+                        g_final.data_ptr(), ws.data_ptr(), nb,
+                        dy0.data_ptr(), dth.data_ptr(), st.data_ptr())
+        self.stream.synchronize()  # the workspace is freed on return
+        return dy0, dth, st
 
     def close(self):
         if getattr(self, "handle", None) is not None:

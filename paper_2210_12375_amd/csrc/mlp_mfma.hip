@@ -279,10 +279,14 @@ __global__ __launch_bounds__(64 * WV) void vjp_mfma_kernel(MfmaVjpArgs a) {
   }
   __syncthreads();
 
-  // row updates
+  // row updates (or, for the continuous adjoint, mu itself)
   for (int idx = tid; idx < PR * D; idx += blockDim.x) {
     const int r = idx / D, c = idx % D, row = r0 + r;
     if (!on(row)) continue;
+    if (a.mu_out != nullptr) {
+      a.mu_out[(long)row * D + c] = c < din ? MU[r * din + c] : 0.f;
+      continue;
+    }
     const float h = a.bh[row];
     float mu = c < din ? MU[r * din + c] : 0.f;
     const long o = (long)row * D + c;

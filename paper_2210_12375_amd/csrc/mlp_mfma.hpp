@@ -78,6 +78,9 @@ struct MfmaVjpArgs {
   int kidx[6];
   float coef[6];
   float *lam, *lamn, *kap;  // kap: [7, B, D]
+  // Continuous adjoint: if not null, mu_s is stored here ([B, D], zero in
+  // the columns the field does not read) instead of the row updates above.
+  float* mu_out;
 };
 
 hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s);

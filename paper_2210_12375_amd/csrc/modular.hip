@@ -789,9 +789,9 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     w.f32 = c.precision == BODE_FP32;
     w.packed = L.take<unsigned char>(mfma_packed_bytes(din, c.mlp_hidden, w.f32));
     w.fvec = L.take<float>(mfma_fvec_elems(din, c.mlp_hidden));
-    if (c.record_cap > 0)
-      w.packedT =
-          L.take<unsigned char>(mfma_packedT_bytes(din, c.mlp_hidden, w.f32));
+    // transposed layers for the VJP kernels (discrete and continuous adjoint)
+    w.packedT =
+        L.take<unsigned char>(mfma_packedT_bytes(din, c.mlp_hidden, w.f32));
   }
   if (m) {
     m->st = st;
@@ -1073,6 +1073,9 @@ struct VjpSpec {
   int kidx[6];
   double coef[6];
   double c;
+  // Continuous adjoint: mu_s = J^T kappa_s is stored here ([B, D]) and the
+  // discrete adjoint's row updates are skipped.
+  void* mu_out;
 };
 
 template <typename R>
@@ -1343,6 +1346,11 @@ __global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
     for (int idx = threadIdx.x; idx < ROWS * D; idx += blockDim.x) {
       const int r = idx / D, c = idx % D, row = r0 + r;
       if (row >= B || b.act[row] != kRunning) continue;
+      if (sp.mu_out != nullptr) {
+        static_cast<R*>(sp.mu_out)[(long)row * D + c] =
+            c < din ? MU[r * din + c] : R(0);
+        continue;
+      }
       const R h = b.bh[row];
       R mu = c < din ? MU[r * din + c] : R(0);
       const long o = (long)row * D + c;
@@ -1431,6 +1439,7 @@ hipError_t vjp(const ModImpl& im, const Mod<R>& m, const Back<R>& b,
       a.lam = b.lam;
       a.lamn = b.lamn;
       a.kap = b.kap;
+      a.mu_out = static_cast<float*>(sp.mu_out);
       return launch_vjp_mfma(a, s);
     }
   }
@@ -1885,6 +1894,8 @@ hipError_t backward_m(ModImpl& im, Mod<R>& m, Back<R>& b, const void* ge,
                                static_cast<R*>(dy0), static_cast<R*>(dth), s);
 }
 
+#include "cadjoint.inc"
+
 }  // namespace
 
 hipError_t modular_backward(ModularPlan& mp, const void* g_y_eval,
@@ -1897,6 +1908,51 @@ hipError_t modular_backward(ModularPlan& mp, const void* g_y_eval,
                               dtheta, s);
   return backward_m<float>(*im, im->mf, im->bf, g_y_eval, g_y_final, dy0,
                            dtheta, s);
+}
+
+size_t modular_cadjoint_bytes(const ModularPlan& mp, int joint) {
+  const ModImpl* im = static_cast<const ModImpl*>(mp.impl);
+  if (!im) return 0;
+  return im->is64 ? ca_layout<double>(im->cfg, joint, nullptr, nullptr)
+                  : ca_layout<float>(im->cfg, joint, nullptr, nullptr);
+}
+
+namespace {
+template <typename R>
+hipError_t cadjoint_m(ModImpl& im, Mod<R>& m, int joint, const void* ge,
+                      const void* gf, void* ws, void* dy0, void* dth,
+                      int32_t* stats, hipStream_t s) {
+  CA<R> c{};
+  ca_layout<R>(im.cfg, joint, ws, &c);
+  c.t0 = m.t0;
+  c.t_end = m.t_end;
+  c.rtol = m.rtol;
+  c.atol = m.atol;
+  c.t_eval = m.t_eval;
+  c.fwd = m.st.status;
+  c.yfin = m.y_final;
+  c.g_eval = static_cast<const R*>(ge);
+  c.g_final = static_cast<const R*>(gf);
+  c.ctrl = m.ctrl;
+  if (im.cfg.method == BODE_TSIT5)
+    return cadjoint_t<R, Tsit5>(im, m, c, static_cast<R*>(dy0),
+                                static_cast<R*>(dth), stats, s);
+  return cadjoint_t<R, Dopri5>(im, m, c, static_cast<R*>(dy0),
+                               static_cast<R*>(dth), stats, s);
+}
+}  // namespace
+
+hipError_t modular_cadjoint(ModularPlan& mp, int joint, const void* g_y_eval,
+                            const void* g_y_final, void* workspace,
+                            void* dy0, void* dtheta, int32_t* stats,
+                            hipStream_t s) {
+  ModImpl* im = static_cast<ModImpl*>(mp.impl);
+  if (!im) return hipErrorInvalidValue;
+  if (im->is64)
+    return cadjoint_m<double>(*im, im->md, joint, g_y_eval, g_y_final,
+                              workspace, dy0, dtheta, stats, s);
+  return cadjoint_m<float>(*im, im->mf, joint, g_y_eval, g_y_final, workspace,
+                           dy0, dtheta, stats, s);
 }
 
 hipError_t modular_run(ModularPlan& mp, int budget, hipStream_t s) {

@@ -37,6 +37,13 @@ hipError_t modular_eval(ModularPlan& mp, const double* t_query, void* y_out,
 hipError_t modular_backward(ModularPlan& mp, const void* g_y_eval,
                             const void* g_y_final, void* dy0, void* dtheta,
                             hipStream_t s);
+// Continuous adjoint of the completed solve (joint 0: per instance, 1:
+// joint); the workspace (modular_cadjoint_bytes) is the caller's.
+size_t modular_cadjoint_bytes(const ModularPlan& mp, int joint);
+hipError_t modular_cadjoint(ModularPlan& mp, int joint, const void* g_y_eval,
+                            const void* g_y_final, void* workspace,
+                            void* dy0, void* dtheta, int32_t* stats,
+                            hipStream_t s);
 void modular_release(ModularPlan& mp);
 
 hipError_t launch_count_equal(const int32_t* a, int n, int32_t v, int32_t* out,

@@ -490,6 +490,42 @@ int solver_backward(bode_solver* s, const void* g_y_eval,
   }
 }
 
+size_t solver_cadjoint_workspace_bytes(const bode_solver* s, int32_t joint) {
+  if (!s || s->cfg.rhs == BODE_RHS_ANALYTIC || (joint != 0 && joint != 1))
+    return 0;
+  return bode::modular_cadjoint_bytes(s->mp, joint);
+}
+
+int solver_cadjoint(bode_solver* s, int32_t joint, const void* g_y_eval,
+                    const void* g_y_final, void* workspace,
+                    size_t workspace_bytes, void* dy0, void* dtheta,
+                    int32_t* stats) {
+  try {
+    if (!s) return fail(nullptr, BODE_EINVAL, "solver is NULL");
+    if (joint != 0 && joint != 1)
+      return fail(s, BODE_EINVAL, "joint must be 0 or 1");
+    if (!g_y_final || !dy0 || !dtheta || !workspace)
+      return fail(s, BODE_EINVAL,
+                  "g_y_final, dy0, dtheta and workspace are required");
+    if (s->cfg.E > 0 && !g_y_eval)
+      return fail(s, BODE_EINVAL, "g_y_eval is required when E > 0");
+    if (s->cfg.rhs == BODE_RHS_ANALYTIC)
+      return fail(s, BODE_EUNSUPPORTED,
+                  "the continuous adjoint is built for MLP and CNF fields");
+    if (!s->stepped) return fail(s, BODE_ESTATE, "no completed solve");
+    const size_t need = bode::modular_cadjoint_bytes(s->mp, joint);
+    if (workspace_bytes < need)
+      return fail(s, BODE_EINVAL,
+                  "workspace too small: need " + std::to_string(need) +
+                      " bytes");
+    HIP_TRY(bode::modular_cadjoint(s->mp, joint, g_y_eval, g_y_final,
+                                   workspace, dy0, dtheta, stats, s->stream));
+    return BODE_OK;
+  } catch (...) {
+    return fail(s, BODE_EHIP, "unknown error in solver_cadjoint");
+  }
+}
+
 int solver_get_stats(const bode_solver* cs, int32_t* n_attempted,
                      int32_t* n_accepted, int32_t* n_rejected,
                      int32_t* n_feval, int32_t* status) {

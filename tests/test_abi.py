@@ -99,4 +99,7 @@ def test_init_validates_before_touching_the_device():
 def test_null_handles_are_rejected():
     assert bd.lib().solver_solve(None) == bd.EINVAL
     assert bd.lib().solver_step(None, 1, None) == bd.EINVAL
+    assert bd.lib().solver_cadjoint(None, 0, None, None, None, 0, None, None,
+                                    None) == bd.EINVAL
+    assert bd.lib().solver_cadjoint_workspace_bytes(None, 0) == 0
     bd.lib().solver_destroy(None)

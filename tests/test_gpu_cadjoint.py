@@ -1,0 +1,135 @@
+"""GPU continuous adjoint (solver_cadjoint, appendix A) against the oracle's
+continuous adjoint of the same forward result (the GPU's y_final and
+statuses are handed to the oracle), per instance and joint.  FP64: the
+backward step counts equal and the gradients agree to 1e-9; FP32 (matrix
+cores where the shape is built): 1e-4; BF16: 1e-2."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import as_float_inputs
+from paper_2210_12375_amd import binding as bd
+from paper_2210_12375_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cotangents(p, seed=0):
+    rng = np.random.default_rng(seed)
+    B, D = p["y0"].shape
+    E = p["t_eval"].shape[1]
+    return (rng.standard_normal((B, E, D)) if E else None,
+            rng.standard_normal((B, D)))
+
+
+def run(p, precision, rhs, joint, g_eval, g_final, method="dopri5"):
+    dp = bd.device_problem(p, precision)
+    s = bd.Solver(dp, method=method, precision=precision, rhs=rhs)
+    s.solve()
+    dt = s.y_final.dtype
+    ge = (None if g_eval is None
+          else torch.as_tensor(g_eval, dtype=dt, device="cuda"))
+    gf = torch.as_tensor(g_final, dtype=dt, device="cuda")
+    P = sum(np.asarray(p["mlp"][k]).size for k in PARAMS)
+    dy0, dth, st = s.cadjoint(ge, gf, P, joint)
+    out = dict(y_final=s.y_final.double().cpu().numpy(),
+               fwd=s.stats()["status"].cpu().numpy(),
+               dy0=dy0.double().cpu().numpy(), dth=dth.double().cpu().numpy(),
+               st=st.cpu().numpy(),
+               ge=None if ge is None else ge.double().cpu().numpy(),
+               gf=gf.double().cpu().numpy())
+    s.close()
+    return out
+
+
+def reference(p, g, joint, method="dopri5"):
+    return oracle.cadjoint(p, g["y_final"], g["fwd"], g["ge"], g["gf"],
+                           joint=joint, method=method)
+
+
+CASES = [("mlp", "dopri5"), ("mlp", "tsit5"), ("cnf", "dopri5")]
+
+
+def problem(kind, B=6, d=8, hidden=16):
+    if kind == "mlp":
+        return W.neural_ode_fit(B=B, d=d, hidden=hidden, n_times=3), \
+            bd.RHS_MLP
+    return W.cnf_density(B=B, d=d, hidden=hidden), bd.RHS_CNF
+
+
+@pytest.mark.parametrize("joint", [0, 1])
+@pytest.mark.parametrize("kind,method", CASES)
+def test_fp64_against_oracle(kind, method, joint):
+    flush(f"cadjoint fp64 {kind} {method} joint={joint}")
+    p, rhs = problem(kind)
+    g_eval, g_final = cotangents(p)
+    g = run(p, "fp64", rhs, joint, g_eval, g_final, method)
+    assert np.all(g["fwd"] == bd.SUCCESS)
+    r = reference(p, g, joint, method)
+    assert np.all(g["st"][4] == bd.SUCCESS)
+    assert np.array_equal(g["st"][0], r["n_attempted"]), (g["st"][0],
+                                                          r["n_attempted"])
+    assert np.array_equal(g["st"][1], r["n_accepted"])
+    assert np.array_equal(g["st"][3], r["n_feval"])
+    e0, e1 = rel(g["dy0"], r["dy0"]), rel(g["dth"], r["dtheta"])
+    flush(f"  dy0 {e0:.2e} dtheta {e1:.2e}")
+    assert e0 <= 1e-9 and e1 <= 1e-9, (e0, e1)
+
+
+@pytest.mark.parametrize("joint", [0, 1])
+@pytest.mark.parametrize("precision,kind,d,hidden", [
+    ("fp32", "mlp", 32, 64),   # FP32 matrix cores
+    ("fp32", "mlp", 24, 48),   # FMA kernels
+    ("bf16", "mlp", 32, 64),
+    ("fp32", "cnf", 16, 64),
+    ("bf16", "cnf", 16, 64),
+])
+def test_reduced_precision_against_oracle(precision, kind, d, hidden, joint):
+    flush(f"cadjoint {precision} {kind} d={d} H={hidden} joint={joint}")
+    p, rhs = problem(kind, B=24, d=d, hidden=hidden)
+    g_eval, g_final = cotangents(p, 1)
+    g = run(p, precision, rhs, joint, g_eval, g_final)
+    assert np.all(g["fwd"] == bd.SUCCESS)
+    assert np.all(g["st"][4] == bd.SUCCESS)
+    r = reference(as_float_inputs(p), g, joint)
+    e0, e1 = rel(g["dy0"], r["dy0"]), rel(g["dth"], r["dtheta"])
+    flush(f"  dy0 {e0:.2e} dtheta {e1:.2e} steps gpu "
+          f"{g['st'][0].sum()} oracle {r['n_attempted'].sum()}")
+    tol = 1e-4 if precision == "fp32" else 1e-2
+    assert e0 <= tol and e1 <= tol, (e0, e1)
+
+
+def test_edges():
+    """An instance with t0 = t_end (no backward steps: dy0 = the cotangents),
+    evaluation times at t0 and at t_end, and joint membership (an instance
+    with other evaluation times is left out of the joint system)."""
+    flush("cadjoint edges")
+    p, rhs = problem("mlp", B=5, d=8, hidden=16)
+    p["t_eval"] = np.tile(np.array([0.0, 0.5, 0.5, 1.0]), (5, 1))
+    p["t_end"][3] = 0.0
+    p["t_eval"][3] = 0.0
+    g_eval, g_final = cotangents(p, 2)
+    for joint in (0, 1):
+        g = run(p, "fp64", rhs, joint, g_eval, g_final)
+        r = reference(p, g, joint)
+        assert np.array_equal(g["st"][4], r["status"])
+        ok = r["status"] != 4
+        assert np.all(np.isnan(g["dy0"][~ok]))
+        assert rel(g["dy0"][ok], r["dy0"][ok]) <= 1e-9
+        assert rel(g["dth"], r["dtheta"]) <= 1e-9
+        if joint:
+            assert r["status"][3] == 4  # other span: not a member
+        else:
+            assert np.allclose(g["dy0"][3], g_final[3] + g_eval[3].sum(0),
+                               rtol=0, atol=1e-12)
