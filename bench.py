@@ -250,6 +250,62 @@ def neural_suite(bd, W, rl, steps, warmup):
     return out
 
 
+def cadjoint_study(bd, W, reps=2):
+    """Appendix A's adjoint-equation backward: the continuous adjoint solved
+    per instance (b (f + p) variables) and jointly (b f + p), beside the
+    discrete adjoint of the same forward solve.  Backward time, steps and
+    time per step; the gradients of the three agree to O(tol)."""
+    import torch
+    out = {}
+    for name, p, rhs, prec in (
+            ("cnf_8192_bf16", W.cnf_density(), bd.RHS_CNF, "bf16"),
+            ("mlp_1024_fp32", W.neural_ode_fit(), bd.RHS_MLP, "fp32")):
+        dp = bd.device_problem(p, prec)
+        P = sum(np.asarray(p["mlp"][k]).size
+                for k in ("W1", "b1", "W2", "b2", "W3", "b3"))
+        s = bd.Solver(dp, method="dopri5", precision=prec, rhs=rhs,
+                      record_cap=256, ckpt_every=2).solve()
+        B, D = p["y0"].shape
+        E = p["t_eval"].shape[1]
+        g_final = torch.ones((B, D), dtype=torch.float32, device="cuda")
+        g_eval = (torch.ones((B, E, D), dtype=torch.float32, device="cuda")
+                  if E else None)
+        r = {"instances": B, "params": P}
+        grads = {}
+        for mode in ("discrete", "per_instance", "joint"):
+            times = []
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "discrete":
+                    dy0, dth = s.backward(g_eval, g_final, P)
+                    st = None
+                else:
+                    dy0, dth, st = s.cadjoint(g_eval, g_final, P,
+                                              joint=mode == "joint")
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            ms = float(np.median(times[1:])) * 1e3
+            grads[mode] = dth.double().cpu().numpy()
+            m = {"ms": round(ms, 3)}
+            if st is not None:
+                att = st[0].cpu().numpy()
+                ok = st[4].cpu().numpy() == 1
+                m["steps"] = int(att.max())
+                m["ms_per_step"] = round(ms / max(1, int(att.max())), 3)
+                m["all_success"] = bool(ok.all())
+            r[mode] = m
+        ref = grads["discrete"]
+        for mode in ("per_instance", "joint"):
+            r[mode]["rel_diff_vs_discrete"] = float(
+                np.linalg.norm(grads[mode] - ref) / np.linalg.norm(ref))
+        s.close()
+        out[name] = r
+        print(f"# continuous adjoint {name}: " + json.dumps(r),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def pid_study(bd, W):
     """Appendix C's controller study: accepted + rejected steps for one Van
     der Pol cycle per mu, integral controller against PI and PID laws on
@@ -417,6 +473,7 @@ def main():
     if not a.no_neural:
         line["neural"] = neural_suite(bd, W, rl, max(2, a.steps // 4),
                                       min(a.warmup, 2))
+        line["cadjoint_study"] = cadjoint_study(bd, W)
     line["pid_study"] = pid_study(bd, W)
     line["joint_study"] = joint_study(bd, W)
     if not a.no_cpu_baseline:

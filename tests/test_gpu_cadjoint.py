@@ -133,3 +133,31 @@ def test_edges():
         else:
             assert np.allclose(g["dy0"][3], g_final[3] + g_eval[3].sum(0),
                                rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision,kind,d,hidden,reps", [
+    ("bf16", "cnf", 16, 512, 100),   # the CNF field of the benchmark
+    ("fp32", "mlp", 32, 384, 200),   # FMA kernels, ragged entry blocks
+])
+def test_per_instance_at_scale_replicated(precision, kind, d, hidden, reps):
+    """Per-instance parameter adjoints of 12 * reps instances (two [B, P]
+    buffers of several GB): 12 distinct instances repeated, so every copy
+    takes its original's steps and dtheta is reps times the oracle's."""
+    flush(f"cadjoint replicated {precision} {kind} H={hidden} reps={reps}")
+    base, rhs = problem(kind, B=12, d=d, hidden=hidden)
+    idx = np.tile(np.arange(12), reps)
+    p = W.subset(base, idx)
+    g_eval0, g_final0 = cotangents(base, 4)
+    g = run(p, precision, rhs, 0, None if g_eval0 is None else g_eval0[idx],
+            g_final0[idx])
+    assert np.all(g["st"][4] == bd.SUCCESS)
+    for r in range(1, reps):
+        assert np.array_equal(g["st"][0][12 * r:12 * r + 12], g["st"][0][:12])
+    sub = dict(y_final=g["y_final"][:12], fwd=g["fwd"][:12],
+               ge=None if g["ge"] is None else g["ge"][:12], gf=g["gf"][:12])
+    r = reference(as_float_inputs(base), sub, 0)
+    e0 = rel(g["dy0"], np.tile(r["dy0"], (reps, 1)))
+    e1 = rel(g["dth"], reps * r["dtheta"])
+    flush(f"  dy0 {e0:.2e} dtheta {e1:.2e}")
+    tol = 1e-4 if precision == "fp32" else 1e-2
+    assert e0 <= tol and e1 <= tol, (e0, e1)
