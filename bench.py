@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-neural", action="store_true",
                     help="skip the neural-field workloads")
+    ap.add_argument("--study", default="", choices=["", "cadjoint"],
+                    help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
                          "the reference kernel for HBM byte counters")
@@ -381,6 +383,10 @@ def main():
     from paper_2210_12375_amd import binding as bd
     from paper_2210_12375_amd import roofline as rl
     from paper_2210_12375_amd import workloads as W
+    if a.study == "cadjoint":
+        print(json.dumps({"cadjoint_study": cadjoint_study(bd, W)}),
+              flush=True)
+        return
 
     p = W.uneven_batch()
     B = p["y0"].shape[0]
