@@ -122,6 +122,11 @@ typedef struct {
                          all their components) and one accept/reject
                          decision.  ANALYTIC fields, record_cap = 0 and
                          keep_dense = 0 only.  0: independent instances.   */
+  int32_t eager;      /* neural fields: 1 launches every kernel of the round
+                         loops directly; 0 (default) captures a block of
+                         rounds (and of continuous-adjoint attempts) into a
+                         HIP graph once per handle / call and replays it.
+                         Results are identical.                             */
 } bode_config;
 
 /* Problem description: device pointers (NULL where not used). */

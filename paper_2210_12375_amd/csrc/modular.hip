@@ -689,7 +689,36 @@ struct ModImpl {
   MfmaWeights mw{};  // packed weights of the matrix-core kernels
   bool is64 = false;
   int32_t* host_running = nullptr;  // pinned
+  // kRoundsPerSync rounds of the per-stage loop, captured once per handle
+  hipGraphExec_t rounds_exec = nullptr;
+  // private stream for captures (the caller's may be the null stream,
+  // which cannot be captured; graphs are replayed on the caller's)
+  hipStream_t cap_stream = nullptr;
 };
+
+// Captures what enqueue(q) launches on the handle's capture stream q into an
+// executable graph (no memset nodes: every fill here is a kernel).
+template <class F>
+hipError_t capture(ModImpl& im, F enqueue, hipGraphExec_t* out) {
+  hipError_t e = hipSuccess;
+  if (im.cap_stream == nullptr)
+    e = hipStreamCreateWithFlags(&im.cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  hipStream_t q = im.cap_stream;
+  e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t ee = enqueue(q);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(q, &g);
+  if (ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return ee;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
 
 namespace {
 
@@ -948,18 +977,34 @@ hipError_t run_rounds(ModImpl& im, Mod<R>& m, int budget, hipStream_t s) {
       return im.cfg.method == BODE_TSIT5 ? run_fused<Tsit5>(im, m, budget, s)
                                          : run_fused<Dopri5>(im, m, budget, s);
   }
+  auto rounds = [&](int n, hipStream_t q) -> hipError_t {
+    for (int r = 0; r < n; ++r) {
+      hipError_t e = im.cfg.method == BODE_TSIT5
+                         ? round_launch<R, Tsit5>(im, m, q)
+                         : round_launch<R, Dopri5>(im, m, q);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   int done = 0;
   while (done < budget) {
     const int chunk = budget - done < kRoundsPerSync ? budget - done
                                                      : kRoundsPerSync;
-    for (int r = 0; r < chunk; ++r) {
-      hipError_t e = im.cfg.method == BODE_TSIT5
-                         ? round_launch<R, Tsit5>(im, m, s)
-                         : round_launch<R, Dopri5>(im, m, s);
-      if (e != hipSuccess) return e;
+    hipError_t e;
+    if (chunk == kRoundsPerSync && !im.cfg.eager) {
+      // a full block of rounds: one graph launch (captured on first use)
+      e = im.rounds_exec != nullptr
+              ? hipSuccess
+              : capture(im,
+                        [&](hipStream_t q) { return rounds(kRoundsPerSync, q); },
+                        &im.rounds_exec);
+      if (e == hipSuccess) e = hipGraphLaunch(im.rounds_exec, s);
+    } else {
+      e = rounds(chunk, s);
     }
+    if (e != hipSuccess) return e;
     done += chunk;
-    hipError_t e = hipMemcpyAsync(im.host_running, m.n_running,
+    e = hipMemcpyAsync(im.host_running, m.n_running,
                                   sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
@@ -1979,6 +2024,8 @@ void modular_release(ModularPlan& mp) {
   ModImpl* im = static_cast<ModImpl*>(mp.impl);
   if (!im) return;
   if (im->host_running) (void)hipHostFree(im->host_running);
+  if (im->rounds_exec) (void)hipGraphExecDestroy(im->rounds_exec);
+  if (im->cap_stream) (void)hipStreamDestroy(im->cap_stream);
   delete im;
   mp.impl = nullptr;
 }

@@ -1,7 +1,9 @@
 // Batched ("modular") solver for neural right-hand sides: the state lives in
-// HBM as [B, D] arrays and each step is a short sequence of kernels (stage
+// HBM as [B, D] arrays.  On the matrix cores a whole solve is one persistent
+// launch; otherwise each step is a short sequence of kernels (stage
 // combination fused into the MLP GEMM prologue, the error norm + controller +
-// commit + dense output), replayed from a captured HIP graph.
+// commit + dense output), eight steps of which are captured once into a HIP
+// graph and replayed between the running-count read-backs.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -161,3 +161,27 @@ def test_per_instance_at_scale_replicated(precision, kind, d, hidden, reps):
     flush(f"  dy0 {e0:.2e} dtheta {e1:.2e}")
     tol = 1e-4 if precision == "fp32" else 1e-2
     assert e0 <= tol and e1 <= tol, (e0, e1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("joint", [0, 1])
+def test_graph_matches_eager(precision, joint):
+    """The backward loop replays a captured graph of 4 attempts between its
+    running-count checks; the eager loop gives bitwise the same result."""
+    flush(f"cadjoint graph vs eager {precision} joint={joint}")
+    p, rhs = problem("cnf", B=20, d=8, hidden=32)
+    g_eval, g_final = cotangents(p, 6)
+    out = []
+    for eager in (0, 1):
+        dp = bd.device_problem(p, precision)
+        s = bd.Solver(dp, precision=precision, rhs=rhs, eager=eager)
+        s.solve()
+        dt = s.y_final.dtype
+        gf = torch.as_tensor(g_final, dtype=dt, device="cuda")
+        P = sum(np.asarray(p["mlp"][k]).size for k in PARAMS)
+        dy0, dth, st = s.cadjoint(None, gf, P, joint)
+        out.append((dy0.cpu().numpy(), dth.cpu().numpy(), st.cpu().numpy()))
+        s.close()
+    for x, y in zip(out[0], out[1]):
+        np.testing.assert_array_equal(x, y)
+    assert out[0][2][0].max() > 4  # more than one replay

@@ -217,3 +217,44 @@ def test_mlp_fp64_pid_parity():
     assert np.all(r["status"] == bd.SUCCESS)
     assert_fp64_parity(g, r)
     replay_check(p, g, "dopri5", c)
+
+
+@pytest.mark.parametrize("precision,opts", [
+    ("fp64", {}),                     # per-stage FMA path
+    ("fp32", {"keep_dense": 1}),      # per-stage matrix-core path
+    ("fp32", {"record_cap": 64}),     # FMA shapes (hidden 48)
+])
+def test_graph_replays_match_eager(precision, opts):
+    """The per-stage round loop replays a captured graph of 8 rounds: a
+    solver stepped 8 attempts at a time (one replay per call, with the
+    read-back and synchronisation between replays) matches a solver that
+    launches every kernel itself, bitwise after every replay."""
+    flush(f"graph replays {precision} {opts}")
+    hidden = 48 if "record_cap" in opts else 64
+    p = W.neural_ode_fit(B=40, d=16, hidden=hidden, n_times=3)
+    p["rtol"][:] = 1e-8  # enough attempts for several replays
+    p["atol"][:] = 1e-9
+    dp = bd.device_problem(p, precision)
+    a = bd.Solver(dp, precision=precision, rhs=bd.RHS_MLP, **opts)
+    b = bd.Solver(dp, precision=precision, rhs=bd.RHS_MLP, eager=1, **opts)
+    replays = 0
+    for _ in range(200):
+        na = a.step(8, want_running=True)
+        nb = b.step(8, want_running=True)
+        replays += 1
+        assert na == nb
+        sa, sb = a.stats(), b.stats()
+        for k in sa:
+            np.testing.assert_array_equal(sa[k].cpu().numpy(),
+                                          sb[k].cpu().numpy())
+        done = sa["status"].cpu().numpy() != bd.RUNNING  # y_final written
+        np.testing.assert_array_equal(a.y_final.cpu().numpy()[done],
+                                      b.y_final.cpu().numpy()[done])
+        if na == 0:
+            break
+    assert na == 0 and replays >= 2
+    for k in ("y_final", "y_eval"):
+        np.testing.assert_array_equal(getattr(a, k).cpu().numpy(),
+                                      getattr(b, k).cpu().numpy())
+    a.close()
+    b.close()
