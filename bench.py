@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-neural", action="store_true",
                     help="skip the neural-field workloads")
-    ap.add_argument("--study", default="", choices=["", "cadjoint"],
+    ap.add_argument("--study", default="", choices=["", "cadjoint", "neural"],
                     help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
@@ -385,6 +385,10 @@ def main():
     from paper_2210_12375_amd import workloads as W
     if a.study == "cadjoint":
         print(json.dumps({"cadjoint_study": cadjoint_study(bd, W)}),
+              flush=True)
+        return
+    if a.study == "neural":
+        print(json.dumps({"neural": neural_suite(bd, W, rl, 2, 1)}),
               flush=True)
         return
 
