@@ -422,7 +422,16 @@ def main():
         flops = rl.analytic_flops(m, p["kind"], p["dim"], st["n_attempted"],
                                   emitted)
         solve_avg = float(np.mean(solve_ms))
+        crit = None
+        if (m, pr) == variants[0]:
+            # the critical path: the instance with the most attempts, alone
+            top = int(np.argmax(st["n_attempted"]))
+            dq = bd.device_problem(W.subset(p, [top]), pr)
+            _, one_ms, _, _, _ = timed_solves(bd, dq, m, pr, 5, 2)
+            crit = dict(instance=top, attempts=int(st["n_attempted"][top]),
+                        alone_ms=float(np.median(one_ms)))
         results[(m, pr)] = dict(
+            crit=crit,
             ms_per_step=wall, solve_ms=solve_avg, accepted=acc,
             attempted=att, value=acc / (wall * 1e-3),
             flops=flops, ok=bool(np.all(st["status"] == 1)),
@@ -467,7 +476,14 @@ def main():
                                  else None),
                      "kernel": "persistent solve (Van der Pol + linear "
                                "kernels, concurrent)",
-                     "critical_path_steps": head["steps_max"]},
+                     "critical_path_steps": head["steps_max"],
+                     # the batch cannot finish before its longest instance:
+                     # that instance solved alone is the latency floor
+                     "critical_path": {
+                         "longest_instance_attempts": head["crit"]["attempts"],
+                         "longest_instance_alone_ms": head["crit"]["alone_ms"],
+                         "batch_solve_ms": head["solve_ms"],
+                         "frac": head["crit"]["alone_ms"] / head["solve_ms"]}},
         "accuracy": {f"{m}/{pr}": {"err_in_tol_units_median":
                                    r["err_at_tol"][0],
                                    "err_in_tol_units_max": r["err_at_tol"][1],
