@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-neural", action="store_true",
                     help="skip the neural-field workloads")
-    ap.add_argument("--study", default="", choices=["", "cadjoint", "neural"],
+    ap.add_argument("--study", default="",
+                    choices=["", "cadjoint", "neural", "ceilings", "hbm"],
                     help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
@@ -159,6 +160,97 @@ def measured_traffic():
     return int(fields["traffic_bytes_per_launch_pair"])
 
 
+def ceilings():
+    """Achievable ceilings beside the datasheet peaks: a streaming triad and
+    a plain device copy for HBM, register-resident MFMA loops (BF16 16x16x32,
+    FP32 16x16x4) and an FP32 FMA loop without packed instructions."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2210_12375_amd",
+                              "libceilings.so"))
+    vp = C.c_void_p
+    lib.ceil_triad.argtypes = [vp, vp, vp, C.c_long, C.c_float, vp]
+    for f in (lib.ceil_mfma_bf16, lib.ceil_mfma_f32, lib.ceil_fma_f32):
+        f.argtypes = [vp, C.c_int, C.c_int, vp]
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(st)
+            fn()
+            b.record(st)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e-3
+
+    def ok(rc):
+        if rc != 0:
+            raise RuntimeError(f"ceilings kernel failed: {rc}")
+
+    n = 256 << 20  # 1 GiB per vector: far beyond every cache
+    a = torch.ones(n, device="cuda")
+    b = torch.ones(n, device="cuda")
+    c = torch.empty(n, device="cuda")
+    t_triad = timed(lambda: ok(lib.ceil_triad(a.data_ptr(), b.data_ptr(),
+                                              c.data_ptr(), n, 0.5,
+                                              st.cuda_stream)))
+    t_copy = timed(lambda: c.copy_(a))
+    del a, b, c
+    blocks, iters = 2048, 20000
+    out = torch.empty(blocks * 256, device="cuda")
+    res = {}
+    for name, fn, fl in (
+            ("mfma_bf16_tflops", lib.ceil_mfma_bf16, 16 * 16 * 32 * 2),
+            ("mfma_f32_tflops", lib.ceil_mfma_f32, 16 * 16 * 4 * 2)):
+        t = timed(lambda: ok(fn(out.data_ptr(), blocks, iters,
+                                st.cuda_stream)), 5)
+        res[name] = blocks * 4 * iters * 8 * fl / t / 1e12
+    t = timed(lambda: ok(lib.ceil_fma_f32(out.data_ptr(), blocks, iters,
+                                          st.cuda_stream)), 5)
+    res["vector_fp32_fma_tflops"] = blocks * 256 * 16 * iters * 2 / t / 1e12
+    res.update(hbm_triad_gbps=12 * n / t_triad / 1e9,
+               hbm_copy_gbps=8 * n / t_copy / 1e9,
+               datasheet={"hbm_gbps": 8000, "mfma_bf16_tflops": 2500,
+                          "mfma_f32_tflops": 157.3,
+                          "vector_fp32_tflops_packed": 157.3,
+                          "vector_fp64_tflops": 78.6})
+    print("# ceilings: " + json.dumps({k: (round(v, 1)
+                                          if isinstance(v, float) else v)
+                                      for k, v in res.items()}),
+          file=sys.stderr, flush=True)
+    return res
+
+
+def hbm_study(bd, W):
+    """The scan-like commit kernel (error norm, controller, commit) out of
+    cache: an MLP field with D = 64 state features on 2^20 instances in FP32
+    on the per-stage path (hidden width 48 runs on the FMA field kernels),
+    so every commit launch streams 10 D floats per instance (the six
+    non-zero error stages, y and the candidate read; y and the FSAL stage
+    written): 2.7 GB per launch.  Its duration comes from the kernel trace
+    of this study."""
+    import torch
+    B = 1 << 20
+    p = W.neural_ode(B=B, d=64, hidden=48)
+    dp = bd.device_problem(p, "fp32")
+    s = bd.Solver(dp, method="dopri5", precision="fp32", rhs=bd.RHS_MLP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    st = {k: v.cpu().numpy() for k, v in s.stats().items()}
+    s.close()
+    att = st["n_attempted"]
+    return {"instances": B, "D": 64, "hidden": 48,
+            "attempts_min": int(att.min()), "attempts_max": int(att.max()),
+            "commit_bytes_per_launch_all_rows": 10 * 64 * 4 * B,
+            "solve_ms": ms, "all_success": bool(np.all(st["status"] == 1))}
+
+
 def cpu_baseline(p, method, seconds):
     """The FP64 oracle on the host cores over whole copies of a bounded
     sample of the same batch."""
@@ -185,6 +277,56 @@ def cpu_baseline(p, method, seconds):
             "sample": f"first {n} of the 65,536 instances (FP64 oracle, "
                       f"{method}, PI), {reps} repetitions, "
                       f"{dt * 1e3:.1f} ms per pass"}
+
+
+def cpu_configs(method="dopri5"):
+    """The FP64 oracle on the host at one thread and at all threads on each
+    workload's sample (the parity batch in full, the first 8192 uneven
+    instances, the first 256 / 64 / 64 neural instances): accepted
+    instance-steps/s for forward solves, instances/s for forward + discrete
+    adjoint.  Context for the GPU figures, not a target."""
+    import oracle
+    from paper_2210_12375_amd import workloads as W
+    nt = os.cpu_count() or 1
+    try:
+        nt = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    P = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def fwd(q, threads):
+        t0 = time.perf_counter()
+        r = oracle.solve(q, method=method, n_threads=threads)
+        return int(r["n_accepted"].sum()) / (time.perf_counter() - t0)
+
+    def fwdbwd(q, threads):
+        t0 = time.perf_counter()
+        r = oracle.solve(q, method=method, n_threads=threads, record_cap=512)
+        h, n = oracle.accepted_steps(r["h_rec"], r["n_attempted"])
+        B, D = q["y0"].shape
+        E = q["t_eval"].shape[1]
+        g_eval = np.ones((B, E, D)) if E else None
+        oracle.adjoint(q, h, n, g_eval, np.ones((B, D)), method=method,
+                       n_threads=threads)
+        return B / (time.perf_counter() - t0)
+
+    out = {"threads": nt}
+    work = (("vdp_64_fp64", W.vdp_batch(), fwd, "accepted instance-steps/s"),
+            ("uneven_first8192", W.subset(W.uneven_batch(), np.arange(8192)),
+             fwd, "accepted instance-steps/s"),
+            ("neural_fwd_first256", W.subset(W.neural_ode(), np.arange(256)),
+             fwd, "accepted instance-steps/s"),
+            ("neural_fwdbwd_first64",
+             W.subset(W.neural_ode_fit(), np.arange(64)), fwdbwd,
+             "fwd+bwd instances/s"),
+            ("cnf_fwdbwd_first64", W.subset(W.cnf_density(), np.arange(64)),
+             fwdbwd, "fwd+bwd instances/s"))
+    for name, q, fn, unit in work:
+        out[name] = {"unit": unit, "one_thread": fn(q, 1),
+                     "all_threads": fn(q, nt)}
+    print("# cpu oracle per workload: " + json.dumps(out), file=sys.stderr,
+          flush=True)
+    return out
 
 
 def neural_suite(bd, W, rl, steps, warmup):
@@ -387,6 +529,12 @@ def main():
         print(json.dumps({"cadjoint_study": cadjoint_study(bd, W)}),
               flush=True)
         return
+    if a.study == "ceilings":
+        print(json.dumps({"ceilings": ceilings()}), flush=True)
+        return
+    if a.study == "hbm":
+        print(json.dumps({"hbm_study": hbm_study(bd, W)}), flush=True)
+        return
     if a.study == "neural":
         print(json.dumps({"neural": neural_suite(bd, W, rl, 2, 1)}),
               flush=True)
@@ -500,10 +648,12 @@ def main():
         line["neural"] = neural_suite(bd, W, rl, max(2, a.steps // 4),
                                       min(a.warmup, 2))
         line["cadjoint_study"] = cadjoint_study(bd, W)
+    line["ceilings"] = ceilings()
     line["pid_study"] = pid_study(bd, W)
     line["joint_study"] = joint_study(bd, W)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.method, a.cpu_seconds)
+        line["cpu_oracle_per_workload"] = cpu_configs(a.method)
     print(json.dumps(line), flush=True)
 
 

@@ -43,6 +43,23 @@ def _compile(src, verbose):
     return obj
 
 
+CEIL_SRC = os.path.join(HERE, "ceilings", "ceilings.hip")
+CEIL_LIB = os.path.join(HERE, "libceilings.so")
+
+
+def build_ceilings(verbose: bool = False) -> str:
+    """The measurement-only ceilings library (bench.py's achievable peaks)."""
+    cmd = [HIPCC] + FLAGS + ["-shared", CEIL_SRC, "-o", CEIL_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on ceilings.hip:\n{r.stdout}\n"
+                           f"{r.stderr}")
+    os.replace(CEIL_LIB + ".tmp", CEIL_LIB)
+    return CEIL_LIB
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
@@ -55,6 +72,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(LIB + ".tmp", LIB)
+    build_ceilings(verbose)
     return LIB
 
 

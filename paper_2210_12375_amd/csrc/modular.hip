@@ -574,7 +574,6 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
       const bool nl = t + double(h) >= te;
       m.last[row] = nl;
       m.hs[row] = nl ? R(te - t) : h;
-      atomicAdd(m.n_running, 1);
     }
   }
   if (status != kRunning) finish_row(m, row, lane, status, cursor);
@@ -928,7 +927,7 @@ dim3 row_grid(int B) {
 
 template <typename R, class M>
 hipError_t round_launch(ModImpl& im, Mod<R>& m, hipStream_t s) {
-  hipError_t e = launch_fill_i32(m.n_running, 1, 0, s);
+  hipError_t e = hipSuccess;
   for (int st = 1; st < 7 && e == hipSuccess; ++st) {
     StageSpec sp = stage_spec<M>(st);
     if (st == 6) sp.yout = m.Y7;
@@ -1004,6 +1003,12 @@ hipError_t run_rounds(ModImpl& im, Mod<R>& m, int budget, hipStream_t s) {
     }
     if (e != hipSuccess) return e;
     done += chunk;
+    // instances still running: one ballot count per wavefront (a count per
+    // row in the commit would serialise B atomics on one counter)
+    e = launch_fill_i32(m.n_running, 1, 0, s);
+    if (e == hipSuccess)
+      e = launch_count_equal(m.st.status, m.B, kRunning, m.n_running, s);
+    if (e != hipSuccess) return e;
     e = hipMemcpyAsync(im.host_running, m.n_running,
                                   sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
