@@ -302,15 +302,23 @@ __device__ __forceinline__ R wave_sum(R v) {
   return v;
 }
 
-template <typename R>
+// Sum over the W lanes (32 or 64) that share a row.
+template <int W, typename R>
+__device__ __forceinline__ R group_sum(R v) {
+#pragma unroll
+  for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename R, int W = 64>
 __device__ __forceinline__ void finish_row(const Mod<R>& m, int row, int lane,
                                            int status, int cursor) {
   const int D = m.D;
-  for (int c = lane; c < D; c += 64)
+  for (int c = lane; c < D; c += W)
     m.y_final[(long)row * D + c] = m.st.y[(long)row * D + c];
   if (status != kSuccess)
     for (int e = cursor; e < m.E; ++e)
-      for (int c = lane; c < D; c += 64)
+      for (int c = lane; c < D; c += W)
         m.y_eval[((long)row * m.E + e) * D + c] = quiet_nan<R>();
 }
 
@@ -455,14 +463,16 @@ __global__ void mod_start_b(Mod<R> m, int probe) {
 }
 
 // Error norm, controller, accept / reject, dense output, commit.
-template <typename R, class M, bool KEEP>
+// One row per W lanes (W = 64: a wavefront; W = 32: half of one, two rows
+// at a time); lane is the row's own lane index in [0, W).
+template <typename R, class M, bool KEEP, int W = 64>
 __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
   if (row >= m.B || m.st.status[row] != kRunning) return;
   const int D = m.D, B = m.B;
   const R hs = m.hs[row];
   const R rt = R(m.rtol[row]), at = R(m.atol[row]);
   R acc = R(0);
-  for (int c = lane; c < D; c += 64) {
+  for (int c = lane; c < D; c += W) {
     R eq = R(0);
 #pragma unroll
     for (int j = 0; j < 7; ++j)
@@ -473,7 +483,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
     const R r = ctl_div(eq, sc);
     acc += r * r;
   }
-  acc = wave_sum(acc);
+  acc = group_sum<W>(acc);
   const R err = ctl_sqrt(ctl_div(acc, R(D)));
   const bool accept = err < R(1);
   const int n_att = m.st.n_att[row] + 1;
@@ -509,7 +519,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
         w[j] = th * (R(M::P[j][0]) +
                      th * (R(M::P[j][1]) +
                            th * (R(M::P[j][2]) + th * R(M::P[j][3]))));
-      for (int cc = lane; cc < D; cc += 64) {
+      for (int cc = lane; cc < D; cc += W) {
         R s2 = R(0);
 #pragma unroll
         for (int j = 0; j < 7; ++j)
@@ -526,7 +536,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
         m.dk.t_prev[row] = t;
         m.dk.h_last[row] = hs;
       }
-      for (int cc = lane; cc < D; cc += 64) {
+      for (int cc = lane; cc < D; cc += W) {
         m.dk.y_prev[(long)row * D + cc] = m.st.y[(long)row * D + cc];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -542,7 +552,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
     const int nacc = m.st.n_acc[row] + 1;
     const bool ck = m.ckpt != nullptr && nacc % m.ck_every == 0 &&
                     nacc / m.ck_every < m.ck_cap;
-    for (int cc = lane; cc < D; cc += 64) {
+    for (int cc = lane; cc < D; cc += W) {
       const R yn = m.Y7[(long)row * D + cc];
       m.st.y[(long)row * D + cc] = yn;
       m.K[(long)row * D + cc] = m.K[((long)6 * B + row) * D + cc];  // FSAL
@@ -576,13 +586,13 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
       m.hs[row] = nl ? R(te - t) : h;
     }
   }
-  if (status != kRunning) finish_row(m, row, lane, status, cursor);
+  if (status != kRunning) finish_row<R, W>(m, row, lane, status, cursor);
 }
 
-template <typename R, class M, bool KEEP>
+template <typename R, class M, bool KEEP, int W>
 __global__ __launch_bounds__(256) void commit_kernel(Mod<R> m) {
-  commit_row<R, M, KEEP>(m, blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6),
-                         threadIdx.x & 63);
+  commit_row<R, M, KEEP, W>(m, blockIdx.x * (blockDim.x / W) + threadIdx.x / W,
+                            threadIdx.x % W);
 }
 
 // ---- fused persistent solve (matrix-core fields) ------------------------------
@@ -621,8 +631,17 @@ __global__ __launch_bounds__(64 * WV) void solve_fused_kernel(Mod<float> m,
       mtile::field_tile<Op, NTW, CNF, WV>(f.st[s], r0, smem_raw);
       __syncthreads();
     }
-    for (int r = wave; r < PR; r += WV)
-      commit_row<float, M, false>(m, r0 + r, lane);
+    // MLP: two rows per wavefront (32 lanes each) while D fits two columns
+    // a lane (364 vs 404 us for 4096 instances); the CNF keeps one row per
+    // wavefront, whose tile kernel is already at the register limit of two
+    // wavefronts per SIMD
+    if (!CNF && m.D <= 64) {
+      for (int r = 2 * wave + (lane >> 5); r < PR; r += 2 * WV)
+        commit_row<float, M, false, 32>(m, r0 + r, lane & 31);
+    } else {
+      for (int r = wave; r < PR; r += WV)
+        commit_row<float, M, false>(m, r0 + r, lane);
+    }
   }
 }
 
@@ -934,12 +953,22 @@ hipError_t round_launch(ModImpl& im, Mod<R>& m, hipStream_t s) {
     e = field<R>(im, m, sp, m.K + (size_t)st * m.B * m.D, s);
   }
   if (e != hipSuccess) return e;
-  if (m.keep)
-    hipLaunchKernelGGL((commit_kernel<R, M, true>), row_grid<R>(m.B),
+  // two rows per wavefront (32 lanes each) while D fits two columns a lane
+  const dim3 g2((m.B + 7) / 8);
+  if (m.D <= 64) {
+    if (m.keep)
+      hipLaunchKernelGGL((commit_kernel<R, M, true, 32>), g2, dim3(256), 0, s,
+                         m);
+    else
+      hipLaunchKernelGGL((commit_kernel<R, M, false, 32>), g2, dim3(256), 0,
+                         s, m);
+  } else if (m.keep) {
+    hipLaunchKernelGGL((commit_kernel<R, M, true, 64>), row_grid<R>(m.B),
                        dim3(256), 0, s, m);
-  else
-    hipLaunchKernelGGL((commit_kernel<R, M, false>), row_grid<R>(m.B),
+  } else {
+    hipLaunchKernelGGL((commit_kernel<R, M, false, 64>), row_grid<R>(m.B),
                        dim3(256), 0, s, m);
+  }
   return hipGetLastError();
 }
 
