@@ -258,3 +258,16 @@ def test_graph_replays_match_eager(precision, opts):
                                       getattr(b, k).cpu().numpy())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("d", [16, 100, 160])
+def test_commit_row_widths(d):
+    """The per-stage commit runs 16, 32 or 64 lanes per row by state width
+    (D <= 64, <= 128, larger): FP64 parity against the oracle for each,
+    with eight evaluation times and a ragged batch."""
+    flush(f"commit widths d={d}")
+    p = W.neural_ode_fit(B=37, d=d, hidden=32, n_times=8)
+    g, _ = run_gpu(p, method="dopri5", rhs=bd.RHS_MLP, record_cap=256)
+    r = oracle.solve(p, method="dopri5")
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
