@@ -12,7 +12,8 @@ The headline runs FP32 (state, norm and controller in float; time in
 double) with Dormand-Prince; FP64 and Tsit5 variants are reported beside it,
 each with its error at the stated tolerance against a tight FP64 solve.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the solver runs on one
+GPU.
 """
 import argparse
 import json
@@ -511,7 +512,7 @@ def joint_study(bd, W):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "the solver runs on one GPU only; "
                                    "--gpus must be 1"}), flush=True)
         sys.exit(2)
     import torch

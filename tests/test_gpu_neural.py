@@ -5,7 +5,7 @@ FP64 mode (FMA field kernel): identical counts and statuses and outputs
 within 1e-9 of the free-running FP64 oracle, plus the decision-by-decision
 replay check.  FP32 mode: the oracle replays the GPU's attempt record on the
 float-rounded inputs, 1e-4.  BF16 mode (MFMA, split-BF16 activations, BF16
-weights): the same replay, 1e-2 (the benchmark spec's bound for a BF16 right-hand
+weights): the same replay, 1e-2 (the stated bound for a BF16 right-hand
 side); step counts reported against FP64.
 """
 import numpy as np
