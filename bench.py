@@ -65,9 +65,11 @@ def copy_calibration(mib):
 
 def ensure_built():
     from paper_2210_12375_amd import binding
+    from paper_2210_12375_amd import build
     if not os.path.exists(binding.LIB_PATH):
-        from paper_2210_12375_amd import build
         build.build()
+    elif not os.path.exists(build.CEIL_LIB):
+        build.build_ceilings()
 
 
 def timed_solves(bd, dp, method, precision, steps, warmup, autotune=False):
@@ -167,8 +169,12 @@ def ceilings():
     FP32 16x16x4) and an FP32 FMA loop without packed instructions."""
     import ctypes as C
     import torch
-    lib = C.CDLL(os.path.join(ROOT, "paper_2210_12375_amd",
-                              "libceilings.so"))
+    try:
+        lib = C.CDLL(os.path.join(ROOT, "paper_2210_12375_amd",
+                                  "libceilings.so"))
+    except OSError as e:  # measurement only: the run goes on without it
+        print(f"# ceilings skipped: {e}", file=sys.stderr, flush=True)
+        return None
     vp = C.c_void_p
     lib.ceil_triad.argtypes = [vp, vp, vp, C.c_long, C.c_float, vp]
     for f in (lib.ceil_mfma_bf16, lib.ceil_mfma_f32, lib.ceil_fma_f32):
