@@ -103,3 +103,17 @@ def test_null_handles_are_rejected():
                                     None) == bd.EINVAL
     assert bd.lib().solver_cadjoint_workspace_bytes(None, 0) == 0
     bd.lib().solver_destroy(None)
+
+
+def test_ceilings_library_exports_its_kernels():
+    """The measurement-only ceilings library (bench.py's achievable peaks)
+    is built beside the solver library and exports its four launchers; its
+    argument checks run on the host."""
+    import ctypes as C
+    from paper_2210_12375_amd import build
+    L = C.CDLL(build.CEIL_LIB)
+    for name in ("ceil_triad", "ceil_mfma_bf16", "ceil_mfma_f32",
+                 "ceil_fma_f32"):
+        assert hasattr(L, name), name
+    L.ceil_mfma_bf16.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    assert L.ceil_mfma_bf16(None, 1, 1, None) != 0  # null output refused
