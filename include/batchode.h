@@ -127,6 +127,13 @@ typedef struct {
                          rounds (and of continuous-adjoint attempts) into a
                          HIP graph once per handle / call and replays it.
                          Results are identical.                             */
+  int32_t fixed_step; /* 1: fixed-step integration (section 3 lists it among
+                         the controllers): every instance steps with its own
+                         h0 (bode_problem.h0 is then required), every attempt
+                         is accepted, the step that would pass t_end is
+                         clipped to end there; the error estimate is not
+                         used.  Not with joint mode or solver_cadjoint.
+                         0: adaptive (the controller above).                */
 } bode_config;
 
 /* Problem description: device pointers (NULL where not used). */

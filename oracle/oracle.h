@@ -110,6 +110,10 @@ typedef struct {
    * made at every step.                                                    */
   int32_t round_state_f32;
   double beta3; /* third controller exponent (PID), see beta1            */
+  /* Fixed-step integration (section 3 names it beside the adaptive
+   * controllers): every instance steps with its own h0 (required), every
+   * attempt is accepted, the step that would pass t_end ends there.        */
+  int32_t fixed_step;
 } orc_options;
 
 /* Solves every instance.  Outputs:

@@ -54,7 +54,7 @@ class _Options(C.Structure):
                 ("replay_final", _ip),
                 ("h_rec", _dp), ("rec_cap", C.c_int32), ("err_rec", _dp),
                 ("hprop_rec", _dp), ("round_state_f32", C.c_int32),
-                ("beta3", C.c_double)]
+                ("beta3", C.c_double), ("fixed_step", C.c_int32)]
 
 
 def _load(variant=None):
@@ -154,7 +154,7 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
           fac_max=10.0,
           max_steps=100000, n_threads=0, h_replay=None, n_replay=None,
           record_cap=0, replay_errors=False, variant=None,
-          replay_final=None, round_state_f32=False):
+          replay_final=None, round_state_f32=False, fixed_step=False):
     """Solves every instance; returns a dict of numpy arrays.
 
     variant="fma" runs the same source compiled with contracted multiply-adds
@@ -166,6 +166,7 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
                  n_threads)
     o.round_state_f32 = int(bool(round_state_f32))
     o.beta3 = beta3
+    o.fixed_step = int(bool(fixed_step))
     if h_replay is not None:
         h_replay = _f64(h_replay)
         n_replay = np.ascontiguousarray(n_replay, dtype=np.int32)

@@ -220,9 +220,9 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
         acc += (eq / sc) * (eq / sc);
       }
       const double err = sqrt(acc / n);
-      int accept = replay ? !replay_reject : err < 1.0;
+      int accept = O->fixed_step || (replay ? !replay_reject : err < 1.0);
       double fac = 1.0;
-      {
+      if (!O->fixed_step) {
         if (!isfinite(err))
           fac = O->fac_min;
         else if (accept) {
@@ -288,6 +288,7 @@ int orc_solve(const orc_problem* P, const orc_options* O, double* y_eval,
     return -1;
   if (P->E > 0 && (!y_eval || !P->t_eval)) return -1;
   if (O->method != ORC_DOPRI5 && O->method != ORC_TSIT5) return -1;
+  if (O->fixed_step && (!P->h0 || O->h_replay)) return -1;
   const int nt = O->n_threads > 0 ? O->n_threads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
   for (int32_t i = 0; i < P->B; ++i) solve_one(P, O, i, y_eval, y_final, stats);

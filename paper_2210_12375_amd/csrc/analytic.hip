@@ -225,7 +225,7 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
   const R err2 = N == 2 ? acc * R(0.5) : ctl_div(acc, R(L.dim));
   constexpr bool kSq = std::is_same<R, float>::value;
   const R err = kSq ? err2 : ctl_sqrt(err2);
-  const bool accept = err < R(1);
+  const bool accept = a.ctrl.fixed || err < R(1);
   if (REC && L.n_att <= a.rec_cap)
     a.h_rec[(long)L.inst * a.rec_cap + L.n_att - 1] =
         accept ? double(hs) : -double(hs);
@@ -255,6 +255,7 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
   fac = rmax(R(c.fac_min), accept ? rmin(R(c.fac_max), fac) : fac);
   fac = (accept && L.prev_rej) ? rmin(R(1), fac) : fac;
   fac = __builtin_isfinite(err) ? fac : R(c.fac_min);
+  fac = c.fixed ? R(1) : fac;  // fixed step: h stays
 
   if (accept) {
     const double tnew = last ? L.te : L.t + double(hs);

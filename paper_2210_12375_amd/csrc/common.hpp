@@ -23,6 +23,7 @@ struct Ctrl {
   double beta1, beta2, safety, fac_min, fac_max;
   int32_t max_steps;
   double beta3;
+  int32_t fixed;  // fixed step: accept every attempt, keep h
 };
 
 // Per-instance solver state kept in the caller's workspace between calls

@@ -485,7 +485,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
   }
   acc = group_sum<W>(acc);
   const R err = ctl_sqrt(ctl_div(acc, R(D)));
-  const bool accept = err < R(1);
+  const bool accept = m.ctrl.fixed || err < R(1);
   const int n_att = m.st.n_att[row] + 1;
   if (lane == 0 && m.h_rec != nullptr && n_att <= m.rec_cap)
     m.h_rec[(long)row * m.rec_cap + n_att - 1] =
@@ -501,6 +501,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
   fac = rmax(R(c.fac_min), accept ? rmin(R(c.fac_max), fac) : fac);
   fac = (accept && m.st.prev_rej[row]) ? rmin(R(1), fac) : fac;
   fac = __builtin_isfinite(err) ? fac : R(c.fac_min);
+  fac = c.fixed ? R(1) : fac;  // fixed step: h stays
 
   double t = m.st.t[row];
   const double te = m.t_end[row];
@@ -886,7 +887,7 @@ void fill_mod(Mod<R>* m, const bode_config& c, const bode_problem& p) {
   m->y_eval = static_cast<R*>(p.y_eval);
   m->y_final = static_cast<R*>(p.y_final);
   m->ctrl = Ctrl{c.beta1, c.beta2, c.safety, c.fac_min, c.fac_max,
-                 c.max_steps, c.beta3};
+                 c.max_steps, c.beta3, c.fixed_step};
 }
 
 template <typename R>

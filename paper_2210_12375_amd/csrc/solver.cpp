@@ -130,6 +130,11 @@ std::string check_config(const bode_config* c) {
                    c->keep_dense != 0))
     return "joint mode is built for analytic fields without record_cap or "
            "keep_dense";
+  if (c->fixed_step != 0 && c->fixed_step != 1)
+    return "fixed_step must be 0 or 1";
+  if (c->eager != 0 && c->eager != 1) return "eager must be 0 or 1";
+  if (c->fixed_step && c->joint)
+    return "fixed_step is not built for joint mode";
   if (c->record_cap < 0) return "record_cap must be >= 0";
   if (c->ckpt_every < 0) return "ckpt_every must be >= 0";
   if (c->ckpt_every > 0 && c->record_cap < 1)
@@ -225,7 +230,7 @@ void fill_analytic_args(bode_solver* s, bode::AnalyticArgs<R>* a) {
   a->y_eval = static_cast<R*>(p.y_eval);
   a->y_final = static_cast<R*>(p.y_final);
   a->ctrl = bode::Ctrl{c.beta1, c.beta2, c.safety, c.fac_min, c.fac_max,
-                       c.max_steps, c.beta3};
+                       c.max_steps, c.beta3, c.fixed_step};
   a->budget = c.max_steps + 1;
 }
 
@@ -315,6 +320,8 @@ int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
     if (cfg->rhs == BODE_RHS_CNF && !p->eps)
       return fail(nullptr, BODE_EINVAL, "CNF needs eps");
     const size_t need = workspace_bytes(*cfg);
+    if (cfg->fixed_step && !p->h0)
+      return fail(nullptr, BODE_EINVAL, "fixed_step needs h0 (the step)");
     if (!workspace) return fail(nullptr, BODE_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
       return fail(nullptr, BODE_EINVAL, "workspace must be 256-byte aligned");
@@ -512,6 +519,9 @@ int solver_cadjoint(bode_solver* s, int32_t joint, const void* g_y_eval,
     if (s->cfg.rhs == BODE_RHS_ANALYTIC)
       return fail(s, BODE_EUNSUPPORTED,
                   "the continuous adjoint is built for MLP and CNF fields");
+    if (s->cfg.fixed_step)
+      return fail(s, BODE_EUNSUPPORTED,
+                  "the continuous adjoint is built for adaptive solves");
     if (!s->stepped) return fail(s, BODE_ESTATE, "no completed solve");
     const size_t need = bode::modular_cadjoint_bytes(s->mp, joint);
     if (workspace_bytes < need)

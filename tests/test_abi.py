@@ -66,7 +66,8 @@ def test_workspace_size_rejects_bad_configs():
     for field, value in [("B", 0), ("D", 0), ("D", 9), ("E", -1),
                          ("method", 5), ("precision", 7), ("rhs", 1),
                          ("max_steps", 0), ("fac_min", 0.0), ("fac_max", 0.5),
-                         ("safety", -1.0), ("record_cap", -2)]:
+                         ("safety", -1.0), ("record_cap", -2),
+                         ("fixed_step", 2), ("eager", 3)]:
         c = bd.make_config(64, 2, 8)
         setattr(c, field, value)
         assert bd.solver_workspace_size(c) == 0, field
@@ -94,6 +95,12 @@ def test_init_validates_before_touching_the_device():
     with pytest.raises(bd.BodeError) as ei:  # misaligned workspace
         bd.solver_init(cfg, prob, 260, 1 << 20, None)
     assert ei.value.code == bd.EINVAL
+    cfg = bd.make_config(64, 2, 8, fixed_step=1)
+    with pytest.raises(bd.BodeError) as ei:  # fixed steps need h0
+        bd.solver_init(cfg, prob, 256, 1 << 20, None)
+    assert ei.value.code == bd.EINVAL and "h0" in bd.solver_last_error()
+    cfg = bd.make_config(64, 2, 8, fixed_step=1, joint=1)
+    assert bd.solver_workspace_size(cfg) == 0  # not built for joint mode
 
 
 def test_null_handles_are_rejected():

@@ -61,6 +61,40 @@ def test_fixed_steps_follow_stability_polynomial(method, rng):
 
 
 @pytest.mark.parametrize("method", METHODS)
+def test_fixed_step_mode_follows_stability_polynomial(method, rng):
+    """The fixed-step mode (every attempt accepted, h = h0 kept) on y' = A y
+    with h0 = T/N (exact in binary) takes N accepted steps and gives
+    y_N = R(hA)^N y0; with h0 that does not divide T the last step is
+    clipped: y = R(rA) R(hA)^(N-1) y0 with r = T - (N-1) h."""
+    D, N, T = 5, 32, 2.0
+    M = rng.standard_normal((2, D, D)) - 2 * np.eye(D)
+    y0 = rng.standard_normal((2, D))
+    p = linear_problem(M, y0, T)
+    p["h0"] = np.full(2, T / N)
+    p["rtol"][:] = 1e-12  # tolerances the adaptive mode could not meet
+    p["atol"][:] = 1e-14
+    r = oracle.solve(p, method=method, fixed_step=True)
+    for i in range(2):
+        R = stability_matrix(method, (T / N) * M[i])
+        ref = np.linalg.matrix_power(R, N) @ y0[i]
+        np.testing.assert_allclose(r["y_final"][i], ref, rtol=1e-12,
+                                   atol=1e-14 * np.abs(ref).max())
+    assert np.all(r["n_accepted"] == N) and np.all(r["n_rejected"] == 0)
+    h = 0.07
+    p["h0"] = np.full(2, h)
+    r = oracle.solve(p, method=method, fixed_step=True)
+    n = int(np.ceil(T / h))
+    t_last = (n - 1) * h
+    for i in range(2):
+        ref = np.linalg.matrix_power(stability_matrix(method, h * M[i]),
+                                     n - 1) @ y0[i]
+        ref = stability_matrix(method, (T - t_last) * M[i]) @ ref
+        np.testing.assert_allclose(r["y_final"][i], ref, rtol=1e-11,
+                                   atol=1e-13 * np.abs(ref).max())
+    assert np.all(r["n_accepted"] == n)
+
+
+@pytest.mark.parametrize("method", METHODS)
 def test_order_five_convergence_on_van_der_pol(method):
     """Global error of fixed-step solves of VdP (mu = 0.5, t in [0, 3])
     against a 30-digit Taylor-series reference (mpmath.odefun) falls at least
