@@ -1553,12 +1553,19 @@ __global__ void copy_r(R* dst, const R* src, long n) {
 // C[m][n] += sum_k Tin[k][m] Tg[k][n] over the k range of this split, added
 // into slot[split] (one owner per entry, so the sum is deterministic).  The
 // augmented C = [W; b] of the three layers, concatenated, is dtheta.  Tape
-// rows are M (inputs) and N (cotangents) wide.
+// rows are M (inputs) and N (cotangents) wide.  blockIdx.y selects one of
+// several independent products of the same shape (the stages of an attempt):
+// its tapes and slots start sin, sg and sslot elements further on.
 template <typename R>
 __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
                                                  long K, int M, int N, int S,
-                                                 R* slots, long P, long off) {
+                                                 R* slots, long P, long off,
+                                                 long sin, long sg,
+                                                 long sslot) {
   constexpr int TM = 64, TN = 64, TK = 16;
+  Tin += blockIdx.y * sin;
+  Tg += blockIdx.y * sg;
+  slots += blockIdx.y * sslot;
   __shared__ R As[TK][TM + 4];
   __shared__ R Bs[TK][TN + 4];
   const int tiles_n = (N + TN - 1) / TN;
@@ -1617,8 +1624,11 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 template <int WM, int WN>
 __global__ __launch_bounds__(256) void grad_gemm_mfma(
     const float* Tin, const float* Tg, long K, int M, int N, int S,
-    float* slots, long P, long off) {
+    float* slots, long P, long off, long sin, long sg, long sslot) {
   constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16;
+  Tin += blockIdx.y * sin;
+  Tg += blockIdx.y * sg;
+  slots += blockIdx.y * sslot;
   // row pitch 16 floats past the tile: the four lane groups of an operand
   // read land 16 banks apart
   constexpr int LA = TM + 16, LB = TN + 16;
@@ -1708,8 +1718,11 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
 // cotangent block, on plain FMAs.
 __global__ __launch_bounds__(512) void grad_gemm_big(
     const float* Tin, int ldin, const float* Tg, long K, int M, int N, int S,
-    float* slots, long P, long off) {
+    float* slots, long P, long off, long sin, long sg, long sslot) {
   constexpr int TT = 256, TK = 16, LA = TT + 16;
+  Tin += blockIdx.y * sin;
+  Tg += blockIdx.y * sg;
+  slots += blockIdx.y * sslot;
   constexpr int NL = TK * TT / 512;  // loads per thread per operand
   __shared__ float As[TK * LA];
   __shared__ float Bs[TK * LA];
@@ -1786,47 +1799,54 @@ __global__ __launch_bounds__(512) void grad_gemm_big(
   if (brow && tid < TT && n0 + tid < N) slot[(long)M * N + n0 + tid] += bacc;
 }
 
+// nb > 1: nb products of the same shape in one launch (grid y), product j
+// reading Tin + j sin and Tg + j sg and adding into its own S slots at
+// slots + j sslot (sslot >= S P).
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
-                            int S, R* slots, long P, long off, hipStream_t s) {
+                            int S, R* slots, long P, long off, hipStream_t s,
+                            int nb = 1, long sin = 0, long sg = 0,
+                            long sslot = 0) {
+  if (nb < 1 || (nb > 1 && sslot < (long)S * P)) return hipErrorInvalidValue;
   // tile shape: narrow where the layer has few inputs or outputs
   const bool f32 = std::is_same<R, float>::value;
   const int tm = !f32 ? 64 : (M <= 32 ? 32 : 128);
   const int tn = !f32 ? 64 : (N <= 32 && M > 32 ? 32 : 128);
   const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
-  // k-splits: a few rounds of workgroups over the chip (about 2048, so the
-  // last round's tail is short), each split at least 256 tape rows long, at
-  // most the S slots there are
-  int splits = (2048 + tiles - 1) / tiles;
+  // k-splits: a few rounds of workgroups over the chip (about 2048 over
+  // all nb products, so the last round's tail is short), each split at
+  // least 256 tape rows long, at most the S slots there are
+  int splits = (2048 + tiles * nb - 1) / (tiles * nb);
   const long by_k = K / 256 > 0 ? K / 256 : 1;
   if (splits > by_k) splits = (int)by_k;
   if (splits > S) splits = S;
-  const dim3 g(tiles * splits), blk(256);
+  const dim3 g(tiles * splits, nb), blk(256);
   if constexpr (std::is_same<R, float>::value) {
-    if (M - 1 >= 256 && N >= 256 && K >= 65536) {
+    if (M - 1 >= 256 && N >= 256 && K * nb >= 65536) {
       // weight rows on 256 x 256 tiles; the bias row is the last input
       // feature and rides with the first row of tiles
       const int Mw = M - 1;
       const int tb = ((Mw + 255) / 256) * ((N + 255) / 256);
-      int sb = (1024 + tb - 1) / tb;
+      int sb = (1024 + tb * nb - 1) / (tb * nb);
       if (sb > by_k) sb = (int)by_k;
       if (sb > S) sb = S;
-      hipLaunchKernelGGL(grad_gemm_big, dim3(tb * sb), dim3(512), 0, s, Tin,
-                         M, Tg, K, Mw, N, sb, slots, P, off);
+      hipLaunchKernelGGL(grad_gemm_big, dim3(tb * sb, nb), dim3(512), 0, s,
+                         Tin, M, Tg, K, Mw, N, sb, slots, P, off, sin, sg,
+                         sslot);
       return hipGetLastError();
     }
     if (tm == 32)
       hipLaunchKernelGGL((grad_gemm_mfma<1, 4>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off);
+                         N, splits, slots, P, off, sin, sg, sslot);
     else if (tn == 32)
       hipLaunchKernelGGL((grad_gemm_mfma<4, 1>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off);
+                         N, splits, slots, P, off, sin, sg, sslot);
     else
       hipLaunchKernelGGL((grad_gemm_mfma<4, 4>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off);
+                         N, splits, slots, P, off, sin, sg, sslot);
   } else {
     hipLaunchKernelGGL(grad_gemm<R>, g, blk, 0, s, Tin, Tg, K, M, N, splits,
-                       slots, P, off);
+                       slots, P, off, sin, sg, sslot);
   }
   return hipGetLastError();
 }
@@ -1836,6 +1856,9 @@ template <typename R>
 __global__ void reduce_slots(const R* slots, int G, long P, R* out) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (p >= P) return;
+  // grid y: independent sums, G slots each, into consecutive outputs
+  slots += blockIdx.y * (long)G * P;
+  out += blockIdx.y * P;
   R acc = R(0);
   for (int g = 0; g < G; ++g) acc += slots[(long)g * P + p];
   out[p] = acc;
