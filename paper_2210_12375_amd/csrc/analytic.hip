@@ -392,12 +392,27 @@ __device__ __forceinline__ bool instance_ok(const AnalyticArgs<R>& a, int i) {
   if (!(rt >= 0.0) || !(at >= 0.0) || (rt == 0.0 && at == 0.0)) return false;
   for (int q = 0; q < dim; ++q)
     if (!__builtin_isfinite(double(a.y0[(long)i * a.D + q]))) return false;
+  // sorted within [t0, t_end]: eight independent loads in flight at a time
+  const double* tr = a.t_eval + (long)i * a.E;
   double prev = t0;
-  for (int e = 0; e < a.E; ++e) {
-    const double v = a.t_eval[(long)i * a.E + e];
-    if (!(v >= prev && v <= te)) return false;
+  bool sorted = true;
+  int e = 0;
+  for (; e + 8 <= a.E; e += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = tr[e + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      sorted &= (v[q] >= prev) & (v[q] <= te);
+      prev = v[q];
+    }
+  }
+  for (; e < a.E; ++e) {
+    const double v = tr[e];
+    sorted &= (v >= prev) & (v <= te);
     prev = v;
   }
+  if (!sorted) return false;
   if (a.h0 != nullptr && !(a.h0[i] > 0.0)) return false;
   return true;
 }
@@ -575,9 +590,23 @@ __device__ __forceinline__ bool joint_member(const AnalyticArgs<R>& a, int i,
                                              int ref) {
   if (a.st.status[i] == kInvalid) return false;
   if (a.t0[i] != a.t0[ref] || a.t_end[i] != a.t_end[ref]) return false;
-  for (int e = 0; e < a.E; ++e)
-    if (a.t_eval[(long)i * a.E + e] != a.t_eval[(long)ref * a.E + e])
-      return false;
+  // same evaluation times: eight pairs of loads in flight at a time
+  const double* ti = a.t_eval + (long)i * a.E;
+  const double* tr = a.t_eval + (long)ref * a.E;
+  bool same = true;
+  int e = 0;
+  for (; e + 8 <= a.E; e += 8) {
+    double u[8], v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      u[q] = ti[e + q];
+      v[q] = tr[e + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) same &= u[q] == v[q];
+  }
+  for (; e < a.E; ++e) same &= ti[e] == tr[e];
+  if (!same) return false;
   if (a.h0 != nullptr && a.h0[i] != a.h0[ref]) return false;
   return true;
 }

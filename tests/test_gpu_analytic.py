@@ -280,3 +280,45 @@ def test_pid_fp32_replay(ctrl):
     flush(f"  steps {g['n_accepted'].mean():.1f} vs FP64 "
           f"{f['n_accepted'].mean():.1f}")
     assert abs(g["n_accepted"].mean() / f["n_accepted"].mean() - 1) < 0.02
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("E", [200, 203])
+def test_dense_outputs_many_per_step(method, E):
+    """Appendix A's Van der Pol shape (mu = 2, one cycle, tol 1e-5) with E
+    evaluation times, about four per accepted step (several emissions per
+    step, each reading the prefetched next time), in FP64 against the
+    oracle."""
+    flush(f"paper vdp E={E} fp64 {method}")
+    p = W.paper_vdp(B=64, E=E)
+    g, _ = run_gpu(p, method=method, **controller("I"))
+    r = oracle.solve(p, method=method, **controller("I"))
+    assert np.all(r["status"] == bd.SUCCESS)
+    assert_fp64_parity(g, r)
+    assert np.median(E / g["n_accepted"]) > 2.0  # several outputs per step
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_step_slices_resume_inside_a_block(precision):
+    """solver_step in slices of 3 attempts resumes each instance with its
+    evaluation cursor mid-row (the prefetched next times reloaded): bitwise
+    the result of one solve."""
+    flush(f"paper vdp slices {precision}")
+    p = W.paper_vdp(B=96, E=203)
+    dp = bd.device_problem(p, precision)
+    one = bd.Solver(dp, method="dopri5", precision=precision,
+                    **bd.I_CONTROLLER).solve()
+    s = bd.Solver(dp, method="dopri5", precision=precision,
+                  **bd.I_CONTROLLER)
+    for _ in range(2000):
+        if s.step(3, want_running=True) == 0:
+            break
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(s.y_eval.cpu().numpy(),
+                                  one.y_eval.cpu().numpy())
+    np.testing.assert_array_equal(s.y_final.cpu().numpy(),
+                                  one.y_final.cpu().numpy())
+    st = s.stats()
+    assert (st["status"].cpu().numpy() == bd.SUCCESS).all()
+    one.close()
+    s.close()
