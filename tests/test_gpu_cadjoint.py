@@ -185,3 +185,39 @@ def test_graph_matches_eager(precision, joint):
     for x, y in zip(out[0], out[1]):
         np.testing.assert_array_equal(x, y)
     assert out[0][2][0].max() > 4  # more than one replay
+
+
+@pytest.mark.parametrize("kind", ["cnf", "mlp"])
+def test_full_size_continuous_agrees_with_discrete(kind):
+    """The benchmark's continuous-adjoint workloads at full size: 8192 CNF
+    instances with a 512-wide field in BF16 (the joint pass forms each
+    attempt's parameter part with the 256 x 256-tile GEMM over all seven
+    stages at once) and 1024 MLP instances in FP32.  The per-instance and
+    joint continuous adjoints and the discrete adjoint of the same forward
+    solve approximate one gradient: dtheta and dy0 agree to well within
+    the solve's tolerance (rtol 1e-5; measured 1e-6), where a wrong stage,
+    slot or tape offset gives an O(1) difference."""
+    flush(f"full-size continuous vs discrete {kind}")
+    if kind == "cnf":
+        p, rhs, prec = W.cnf_density(), bd.RHS_CNF, "bf16"
+    else:
+        p, rhs, prec = W.neural_ode_fit(), bd.RHS_MLP, "fp32"
+    dp = bd.device_problem(p, prec)
+    P = sum(np.asarray(p["mlp"][k]).size for k in PARAMS)
+    s = bd.Solver(dp, method="dopri5", precision=prec, rhs=rhs,
+                  record_cap=256, ckpt_every=2).solve()
+    B, D = p["y0"].shape
+    E = p["t_eval"].shape[1]
+    gf = torch.ones((B, D), dtype=torch.float32, device="cuda")
+    ge = (torch.ones((B, E, D), dtype=torch.float32, device="cuda")
+          if E else None)
+    dy0_d, dth_d = s.backward(ge, gf, P)
+    ref0, ref1 = dy0_d.double().cpu().numpy(), dth_d.double().cpu().numpy()
+    for joint in (0, 1):
+        dy0, dth, st = s.cadjoint(ge, gf, P, joint)
+        assert np.all(st[4].cpu().numpy() == bd.SUCCESS)
+        e0 = rel(dy0.double().cpu().numpy(), ref0)
+        e1 = rel(dth.double().cpu().numpy(), ref1)
+        flush(f"  joint={joint}: dy0 {e0:.2e} dtheta {e1:.2e}")
+        assert e0 <= 1e-4 and e1 <= 1e-4, (joint, e0, e1)
+    s.close()
