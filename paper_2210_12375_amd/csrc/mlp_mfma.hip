@@ -76,8 +76,13 @@ hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
 // (plus the CNF's second-order term), S1 = G2 W2^T, G1 = tanh'(p1) S1,
 // mu = G1 W1^T.  For the CNF, gbar's tangent rows hold -kappa_l eps, the
 // cotangent of the tangent output.
+// The CNF kernel at width 512 asks for four wavefronts per SIMD (two
+// workgroups per compute unit): it spills a few registers, but the second
+// workgroup hides more of the three-layer dependent chain (measured 156 ->
+// 133 us per stage for 8192 instances).
 template <class Op, int NTW, bool CNF, int WV>
-__global__ __launch_bounds__(64 * WV) void vjp_mfma_kernel(MfmaVjpArgs a) {
+__global__ __launch_bounds__(64 * WV) __attribute__((
+    amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_mfma_kernel(MfmaVjpArgs a) {
   typedef typename Op::A A;
   typedef typename Op::W W;
   constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 16 * WV,
