@@ -17,7 +17,8 @@
  *    are borrowed: they must stay valid and unchanged until solver_destroy()
  *    (the backward pass re-reads y0 and the parameters).  The library never
  *    allocates device memory: all scratch lives in the caller's workspace of
- *    solver_workspace_size() bytes.
+ *    solver_workspace_size() bytes (solver_solve_noalloc instead uses one
+ *    static device array that the library's code object holds per GPU).
  *  - All device work is enqueued on the caller's stream (a hipStream_t passed
  *    as void*) and is asynchronous unless a call says otherwise.
  *  - Per-instance numerical outcomes are a status (BODE_SUCCESS,
@@ -183,6 +184,25 @@ int solver_step(bode_solver* s, int32_t n_attempts, int32_t* n_running_host);
 /* Steps every instance to completion (t_end, max_steps or a failure).
  * Asynchronous.                                                             */
 int solver_solve(bode_solver* s);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * solver_init + solver_solve in one call with the same kernels and results,
+ * but the workspace is a static device array owned by the library
+ * (32 MiB per GPU, held from the library's load until the process ends)
+ * instead of caller memory; no device memory is allocated or freed.
+ * Analytic right-hand sides only (BODE_EUNSUPPORTED otherwise); a
+ * configuration whose solver_workspace_size() exceeds 32 MiB is rejected
+ * with BODE_EINVAL.  p is as for solver_init (inputs read, y_eval and
+ * y_final written).  stats (device int32 [5, B], may be NULL) receives the
+ * attempted, accepted and rejected steps, evaluations and status of every
+ * instance.  Asynchronous on `stream`.  Every call on one GPU uses that
+ * GPU's one array and leaves its contents behind: calls that overlap on one
+ * GPU (other streams or threads) race and must be ordered by the caller.
+ * There is no handle, so solver_step, solver_eval and the backward passes
+ * are not available for such a solve.                                      */
+int solver_solve_noalloc(const bode_config* cfg, const bode_problem* p,
+                         int32_t* stats, void* stream);
 
 /* Dense output of each instance's last accepted step at its own query time:
  * for t_query[i] in [t_prev_i, t_i] writes y_out[i, :] and qstatus[i] = 0,

@@ -38,7 +38,8 @@ EXPORTED = ["solver_workspace_size", "solver_init", "solver_step",
             "solver_solve", "solver_eval", "solver_backward",
             "solver_cadjoint_workspace_bytes", "solver_cadjoint",
             "solver_get_stats", "solver_get_steps", "solver_autotune",
-            "solver_destroy", "solver_last_error", "solver_tableau"]
+            "solver_destroy", "solver_last_error", "solver_tableau",
+            "solver_solve_noalloc"]
 
 
 class Config(C.Structure):
@@ -112,6 +113,8 @@ def lib():
         L.solver_destroy.argtypes = [vp]
         L.solver_last_error.restype = C.c_char_p
         L.solver_last_error.argtypes = [vp]
+        L.solver_solve_noalloc.restype = C.c_int
+        L.solver_solve_noalloc.argtypes = [cp, C.POINTER(Problem), ip, vp]
         L.solver_tableau.restype = C.c_int
         L.solver_tableau.argtypes = [C.c_int32, vp, vp, vp, vp, vp]
         _lib = L
@@ -170,6 +173,11 @@ def solver_step(h, n_attempts, want_running=False):
 
 def solver_solve(h):
     _check(lib().solver_solve(h), h)
+
+
+def solver_solve_noalloc(cfg, prob, stats_ptr, stream_ptr):
+    _check(lib().solver_solve_noalloc(C.byref(cfg), C.byref(prob), stats_ptr,
+                                      stream_ptr))
 
 
 def solver_eval(h, t_query_ptr, y_out_ptr, qstatus_ptr):

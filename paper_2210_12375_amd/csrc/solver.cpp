@@ -19,6 +19,7 @@
 #include "analytic.hpp"
 #include "common.hpp"
 #include "modular.hpp"
+#include "noalloc.hpp"
 #include "tableau.hpp"
 
 namespace {
@@ -146,6 +147,24 @@ std::string check_config(const bode_config* c) {
   return "";
 }
 
+// Host-visible checks of the problem description (the device inputs are
+// checked per instance by the initialisation kernels).
+std::string check_problem(const bode_config& c, const bode_problem* p) {
+  if (!p) return "problem is NULL";
+  if (!p->y0 || !p->t0 || !p->t_end || !p->rtol || !p->atol || !p->y_final)
+    return "y0, t0, t_end, rtol, atol and y_final are required";
+  if (c.E > 0 && (!p->t_eval || !p->y_eval))
+    return "E > 0 needs t_eval and y_eval";
+  if (c.rhs == BODE_RHS_ANALYTIC && (!p->kind || !p->dim))
+    return "analytic batches need kind and dim";
+  if (c.rhs != BODE_RHS_ANALYTIC &&
+      (!p->W1 || !p->b1 || !p->W2 || !p->b2 || !p->W3 || !p->b3))
+    return "neural fields need W1..b3";
+  if (c.rhs == BODE_RHS_CNF && !p->eps) return "CNF needs eps";
+  if (c.fixed_step && !p->h0) return "fixed_step needs h0 (the step)";
+  return "";
+}
+
 template <typename R>
 size_t layout_analytic(const bode_config& c, void* base,
                        bode::AnalyticArgs<R>* a, int32_t** counts,
@@ -234,6 +253,76 @@ void fill_analytic_args(bode_solver* s, bode::AnalyticArgs<R>* a) {
   a->budget = c.max_steps + 1;
 }
 
+// Launch shapes: the autotuned ones for this shape, overridden by the
+// configuration's explicit tune fields.
+void apply_tune(bode_solver* s) {
+  const bode_config& c = s->cfg;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(c));
+    if (it != g_tune.end()) s->tune = it->second;
+  }
+  if (c.tune_block > 0) s->tune.block = c.tune_block;
+  if (c.tune_lanes > 0) s->tune.lanes_vdp = s->tune.lanes_lin = c.tune_lanes;
+}
+
+// Per-device resources of solver_solve_noalloc, set up on its first call on
+// a device (with that device current) and kept for the life of the process:
+// the address of the device's copy of the static scratch array, the second
+// stream of the analytic solve and the two events that fork and join it.
+struct NoallocDevice {
+  void* scratch = nullptr;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_noalloc_mu;
+std::map<int, NoallocDevice> g_noalloc;
+
+hipError_t noalloc_device(NoallocDevice* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc.find(dev);
+  if (it != g_noalloc.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  NoallocDevice d;
+  e = bode::noalloc_scratch(&d.scratch);
+  if (e != hipSuccess) return e;
+  e = aux_stream(&d.aux);
+  if (e != hipSuccess) return e;
+  e = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = hipEventCreateWithFlags(&d.join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(d.fork);
+    return e;
+  }
+  g_noalloc[dev] = d;
+  *out = d;
+  return hipSuccess;
+}
+
+// Lays out the analytic plan in s->ws and enqueues the initialisation (the
+// work-queue counters are cleared by a fill kernel, not a memset).
+template <typename R>
+hipError_t start_analytic_t(bode_solver* s, bode::AnalyticArgs<R>* a) {
+  const bode_config& c = s->cfg;
+  layout_analytic<R>(c, s->ws, a, &s->counts, &s->n_running_dev);
+  fill_analytic_args<R>(s, a);
+  hipError_t e = bode::launch_fill_i32(s->counts, 8, 0, s->stream);
+  if (e != hipSuccess) return e;
+  return c.joint ? bode::launch_joint_init<R>(*a, c.method, s->stream)
+                 : bode::launch_analytic_init<R>(*a, c.method, s->stream);
+}
+
+hipError_t start_analytic(bode_solver* s) {
+  return is64(s->cfg) ? start_analytic_t<double>(s, &s->ad)
+                      : start_analytic_t<float>(s, &s->af);
+}
+
 #define HIP_TRY(expr)                                                    \
   do {                                                                   \
     hipError_t e_ = (expr);                                              \
@@ -306,22 +395,9 @@ int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
     *out = nullptr;
     const std::string msg = check_config(cfg);
     if (!msg.empty()) return fail(nullptr, BODE_EINVAL, msg);
-    if (!p) return fail(nullptr, BODE_EINVAL, "problem is NULL");
-    if (!p->y0 || !p->t0 || !p->t_end || !p->rtol || !p->atol || !p->y_final)
-      return fail(nullptr, BODE_EINVAL,
-                  "y0, t0, t_end, rtol, atol and y_final are required");
-    if (cfg->E > 0 && (!p->t_eval || !p->y_eval))
-      return fail(nullptr, BODE_EINVAL, "E > 0 needs t_eval and y_eval");
-    if (cfg->rhs == BODE_RHS_ANALYTIC && (!p->kind || !p->dim))
-      return fail(nullptr, BODE_EINVAL, "analytic batches need kind and dim");
-    if (cfg->rhs != BODE_RHS_ANALYTIC &&
-        (!p->W1 || !p->b1 || !p->W2 || !p->b2 || !p->W3 || !p->b3))
-      return fail(nullptr, BODE_EINVAL, "neural fields need W1..b3");
-    if (cfg->rhs == BODE_RHS_CNF && !p->eps)
-      return fail(nullptr, BODE_EINVAL, "CNF needs eps");
+    const std::string pmsg = check_problem(*cfg, p);
+    if (!pmsg.empty()) return fail(nullptr, BODE_EINVAL, pmsg);
     const size_t need = workspace_bytes(*cfg);
-    if (cfg->fixed_step && !p->h0)
-      return fail(nullptr, BODE_EINVAL, "fixed_step needs h0 (the step)");
     if (!workspace) return fail(nullptr, BODE_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
       return fail(nullptr, BODE_EINVAL, "workspace must be 256-byte aligned");
@@ -340,14 +416,7 @@ int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
     s->ws = workspace;
     s->ws_bytes = workspace_bytes_;
     s->stream = static_cast<hipStream_t>(stream);
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      auto it = g_tune.find(tune_key(*cfg));
-      if (it != g_tune.end()) s->tune = it->second;
-    }
-    if (cfg->tune_block > 0) s->tune.block = cfg->tune_block;
-    if (cfg->tune_lanes > 0) s->tune.lanes_vdp = s->tune.lanes_lin =
-        cfg->tune_lanes;
+    apply_tune(s);
 
     if (cfg->rhs == BODE_RHS_ANALYTIC) {
       if (aux_stream(&s->aux) != hipSuccess ||
@@ -358,28 +427,7 @@ int solver_init(const bode_config* cfg, const bode_problem* p, void* workspace,
         solver_destroy(s);
         return fail(nullptr, BODE_EHIP, "cannot create stream/events");
       }
-      hipError_t e;
-      if (is64(*cfg)) {
-        layout_analytic<double>(*cfg, workspace, &s->ad, &s->counts,
-                                &s->n_running_dev);
-        fill_analytic_args<double>(s, &s->ad);
-        e = bode::launch_fill_i32(s->counts, 8, 0, s->stream);
-        if (e == hipSuccess)
-          e = cfg->joint ? bode::launch_joint_init<double>(s->ad, cfg->method,
-                                                   s->stream)
-                         : bode::launch_analytic_init<double>(s->ad, cfg->method,
-                                                      s->stream);
-      } else {
-        layout_analytic<float>(*cfg, workspace, &s->af, &s->counts,
-                               &s->n_running_dev);
-        fill_analytic_args<float>(s, &s->af);
-        e = bode::launch_fill_i32(s->counts, 8, 0, s->stream);
-        if (e == hipSuccess)
-          e = cfg->joint ? bode::launch_joint_init<float>(s->af, cfg->method,
-                                                   s->stream)
-                         : bode::launch_analytic_init<float>(s->af, cfg->method,
-                                                      s->stream);
-      }
+      const hipError_t e = start_analytic(s);
       if (e != hipSuccess) {
         std::string m = std::string("init launch: ") + hipGetErrorString(e);
         solver_destroy(s);
@@ -437,6 +485,74 @@ int solver_solve(bode_solver* s) {
     return rc;
   } catch (...) {
     return fail(s, BODE_EHIP, "unknown error in solver_solve");
+  }
+}
+
+int solver_solve_noalloc(const bode_config* cfg, const bode_problem* p,
+                         int32_t* stats, void* stream) {
+  try {
+    const std::string msg = check_config(cfg);
+    if (!msg.empty()) return fail(nullptr, BODE_EINVAL, msg);
+    const std::string pmsg = check_problem(*cfg, p);
+    if (!pmsg.empty()) return fail(nullptr, BODE_EINVAL, pmsg);
+    if (cfg->rhs != BODE_RHS_ANALYTIC)
+      return fail(nullptr, BODE_EUNSUPPORTED,
+                  "solver_solve_noalloc is built for analytic fields");
+    const size_t need = workspace_bytes(*cfg);
+    if (need > bode::kNoallocBytes)
+      return fail(nullptr, BODE_EINVAL,
+                  "problem needs " + std::to_string(need) +
+                      " bytes of workspace; solver_solve_noalloc holds " +
+                      std::to_string(bode::kNoallocBytes));
+    NoallocDevice dev;
+    hipError_t e = noalloc_device(&dev);
+    if (e != hipSuccess)
+      return fail(nullptr, BODE_EHIP,
+                  std::string("scratch set-up: ") + hipGetErrorString(e));
+    // A handle that lives for this call only; it owns nothing (the events
+    // and the second stream are the device's).
+    bode_solver s;
+    s.cfg = *cfg;
+    s.p = *p;
+    s.ws = dev.scratch;
+    s.ws_bytes = bode::kNoallocBytes;
+    s.stream = static_cast<hipStream_t>(stream);
+    s.aux = dev.aux;
+    s.ev_fork = dev.fork;
+    s.ev_join = dev.join;
+    apply_tune(&s);
+    e = start_analytic(&s);
+    if (e != hipSuccess)
+      return fail(nullptr, BODE_EHIP,
+                  std::string("init launch: ") + hipGetErrorString(e));
+    const int rc = run_steps(&s, cfg->max_steps + 1);
+    if (rc != BODE_OK) return fail(nullptr, rc, s.err);
+    if (stats) {
+      const auto copy = [&](const int32_t* src, int row) {
+        return hipMemcpyAsync(stats + (size_t)row * cfg->B, src,
+                              sizeof(int32_t) * cfg->B,
+                              hipMemcpyDeviceToDevice, s.stream);
+      };
+      const int32_t* src[5];
+      if (is64(*cfg)) {
+        const auto& st = s.ad.st;
+        src[0] = st.n_att, src[1] = st.n_acc, src[2] = st.n_rej,
+        src[3] = st.n_fe, src[4] = st.status;
+      } else {
+        const auto& st = s.af.st;
+        src[0] = st.n_att, src[1] = st.n_acc, src[2] = st.n_rej,
+        src[3] = st.n_fe, src[4] = st.status;
+      }
+      for (int k = 0; k < 5; ++k) {
+        e = copy(src[k], k);
+        if (e != hipSuccess)
+          return fail(nullptr, BODE_EHIP,
+                      std::string("statistics copy: ") + hipGetErrorString(e));
+      }
+    }
+    return BODE_OK;
+  } catch (...) {
+    return fail(nullptr, BODE_EHIP, "unknown error in solver_solve_noalloc");
   }
 }
 

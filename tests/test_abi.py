@@ -124,3 +124,32 @@ def test_ceilings_library_exports_its_kernels():
         assert hasattr(L, name), name
     L.ceil_mfma_bf16.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
     assert L.ceil_mfma_bf16(None, 1, 1, None) != 0  # null output refused
+
+
+def test_noalloc_solve_validates_before_touching_the_device():
+    """The static-scratch entry point rejects, on the host, configurations
+    whose workspace exceeds its 32 MiB array and right-hand sides it is not
+    built for."""
+    prob = bd.Problem()
+    for k in ("y0", "t0", "t_end", "rtol", "atol", "y_final", "t_eval",
+              "y_eval", "kind", "dim", "W1", "b1", "W2", "b2", "W3", "b3"):
+        setattr(prob, k, 256)
+    small = bd.make_config(64, 2, 8)
+    assert bd.solver_workspace_size(small) <= 32 << 20
+    big = bd.make_config(1 << 20, 8, 16, record_cap=8)
+    assert bd.solver_workspace_size(big) > 32 << 20
+    with pytest.raises(bd.BodeError) as ei:
+        bd.solver_solve_noalloc(big, prob, None, None)
+    assert ei.value.code == bd.EINVAL and "33554432" in bd.solver_last_error()
+    mlp = bd.make_config(64, 64, 0, rhs=bd.RHS_MLP, mlp_hidden=256)
+    with pytest.raises(bd.BodeError) as ei:
+        bd.solver_solve_noalloc(mlp, prob, None, None)
+    assert ei.value.code == bd.EUNSUPPORTED
+    bad = bd.make_config(64, 2, 8)
+    bad.B = 0
+    with pytest.raises(bd.BodeError) as ei:
+        bd.solver_solve_noalloc(bad, prob, None, None)
+    assert ei.value.code == bd.EINVAL
+    with pytest.raises(bd.BodeError) as ei:  # missing inputs
+        bd.solver_solve_noalloc(small, bd.Problem(), None, None)
+    assert ei.value.code == bd.EINVAL
