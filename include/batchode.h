@@ -128,8 +128,10 @@ typedef struct {
                          rounds (and of continuous-adjoint attempts) into a
                          HIP graph once per handle / call and replays it.
                          Results are identical.                             */
-  int32_t fixed_step; /* 1: fixed-step integration (section 3 lists it among
-                         the controllers): every instance steps with its own
+  int32_t fixed_step; /* 1: fixed-step integration (a validation mode, not
+                         one of the paper's controllers; its closed form
+                         R(hA)^N y0 checks the stage arithmetic without a
+                         controller): every instance steps with its own
                          h0 (bode_problem.h0 is then required), every attempt
                          is accepted, the step that would pass t_end is
                          clipped to end there; the error estimate is not
@@ -268,6 +270,15 @@ int solver_get_stats(const bode_solver* s, int32_t* n_attempted,
  * and n [B] (int32): the number of attempts (it may exceed record_cap, in
  * which case only the first record_cap are kept).                          */
 int solver_get_steps(const bode_solver* s, double* h, int32_t* n);
+
+/* The weighted RMS error norm of every recorded attempt (section 3: each
+ * instance decides on its own error estimate), copied into the device array
+ * err [B, record_cap] (double) beside solver_get_steps' record: the value
+ * the controller used, so an attempt was accepted exactly when its norm is
+ * below 1 (always, in fixed-step mode).  In FP32 and BF16 modes the norm is
+ * the float value widened to double.  Needs record_cap > 0 (BODE_ESTATE
+ * otherwise).                                                              */
+int solver_get_errors(const bode_solver* s, double* err);
 
 /* Times launch candidates for this configuration on the caller's problem
  * (outputs are overwritten) and keeps the fastest for later solver_init

@@ -107,11 +107,14 @@ typedef struct {
   /* Rounding probe for the tests (not part of the method): when nonzero the
    * state is rounded to the nearest float after every accepted step, which
    * shows how strongly the trajectory amplifies float-sized perturbations
-   * made at every step.                                                    */
+   * made at every step; 2 also rounds every stage input and every stage
+   * derivative to float, so each attempt's error norm carries the rounding
+   * noise a float datapath puts into it (its distance from the plain
+   * replay's norm measures how strongly that noise moves the norm).        */
   int32_t round_state_f32;
   double beta3; /* third controller exponent (PID), see beta1            */
-  /* Fixed-step integration (section 3 names it beside the adaptive
-   * controllers): every instance steps with its own h0 (required), every
+  /* Fixed-step integration (a validation mode; the paper's section 3 names
+   * only adaptive controllers): every instance steps with its own h0 (required), every
    * attempt is accepted, the step that would pass t_end ends there.        */
   int32_t fixed_step;
 } orc_options;

@@ -159,12 +159,14 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
 
     variant="fma" runs the same source compiled with contracted multiply-adds
     and round_state_f32=True rounds the state to float after every accepted
-    step (rounding probes for the tests, not references)."""
+    step; round_state_f32="stages" also rounds every stage input and stage
+    derivative to float (rounding probes for the tests, not references)."""
     lib = _load(variant)
     m = _Marshalled(problem)
     o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps,
                  n_threads)
-    o.round_state_f32 = int(bool(round_state_f32))
+    o.round_state_f32 = (2 if round_state_f32 == "stages"
+                         else int(bool(round_state_f32)))
     o.beta3 = beta3
     o.fixed_step = int(bool(fixed_step))
     if h_replay is not None:

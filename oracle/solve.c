@@ -205,7 +205,11 @@ static void solve_one(const orc_problem* P, const orc_options* O, int32_t i,
           for (int j = 0; j < s; ++j) acc += a[s][j] * k[j][q];
           Y[q] = y[q] + hs * acc;
         }
+        if (O->round_state_f32 == 2) /* float-datapath probe, see oracle.h */
+          for (int q = 0; q < n; ++q) Y[q] = (double)(float)Y[q];
         orc_rhs(P, i, t + c[s] * hs, Y, k[s]);
+        if (O->round_state_f32 == 2)
+          for (int q = 0; q < n; ++q) k[s][q] = (double)(float)k[s][q];
       }
       memcpy(ynew, Y, sizeof(double) * n); /* SSAL: stage 7 input is y_n+1 */
       nfe += 6;

@@ -22,11 +22,15 @@ class ODESolve(torch.autograd.Function):
         s = bd.Solver(dp, **opts)
         s.solve()
         ctx.solver = s
+        # The handle borrows these tensors and solver_backward re-reads them;
+        # saving them lets torch refuse a backward after an in-place change.
+        ctx.save_for_backward(y0, W1, b1, W2, b2, W3, b3)
         ctx.shapes = [t.shape for t in (W1, b1, W2, b2, W3, b3)]
         return s.y_eval.clone(), s.y_final.clone()
 
     @staticmethod
     def backward(ctx, g_eval, g_final):
+        ctx.saved_tensors  # raises if an input was modified in place
         s = ctx.solver
         n = sum(int(torch.Size(sh).numel()) for sh in ctx.shapes)
         if g_eval is None:

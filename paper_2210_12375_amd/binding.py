@@ -39,7 +39,7 @@ EXPORTED = ["solver_workspace_size", "solver_init", "solver_step",
             "solver_cadjoint_workspace_bytes", "solver_cadjoint",
             "solver_get_stats", "solver_get_steps", "solver_autotune",
             "solver_destroy", "solver_last_error", "solver_tableau",
-            "solver_solve_noalloc"]
+            "solver_solve_noalloc", "solver_get_errors"]
 
 
 class Config(C.Structure):
@@ -106,6 +106,8 @@ def lib():
         L.solver_get_stats.argtypes = [vp, ip, ip, ip, ip, ip]
         L.solver_get_steps.restype = C.c_int
         L.solver_get_steps.argtypes = [vp, dp, ip]
+        L.solver_get_errors.restype = C.c_int
+        L.solver_get_errors.argtypes = [vp, dp]
         L.solver_autotune.restype = C.c_int
         L.solver_autotune.argtypes = [cp, C.POINTER(Problem), vp, C.c_size_t,
                                       vp]
@@ -206,6 +208,10 @@ def solver_get_stats(h, *ptrs):
 
 def solver_get_steps(h, h_ptr, n_ptr):
     _check(lib().solver_get_steps(h, h_ptr, n_ptr), h)
+
+
+def solver_get_errors(h, err_ptr):
+    _check(lib().solver_get_errors(h, err_ptr), h)
 
 
 def solver_autotune(cfg, prob, workspace_ptr, workspace_bytes, stream_ptr):
@@ -336,6 +342,14 @@ class Solver:
         n = torch.empty(self.B, dtype=torch.int32, device=self.y_final.device)
         solver_get_steps(self.handle, h.data_ptr(), n.data_ptr())
         return h, n
+
+    def errors(self):
+        """[B, record_cap] error norm of every recorded attempt."""
+        torch = self.torch
+        e = torch.empty((self.B, self.cfg.record_cap), dtype=torch.float64,
+                        device=self.y_final.device)
+        solver_get_errors(self.handle, e.data_ptr())
+        return e
 
     def eval(self, t_query):
         torch = self.torch

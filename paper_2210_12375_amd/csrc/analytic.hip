@@ -76,9 +76,19 @@ __host__ __device__ constexpr bool dense_uses(int j) {
 
 // ---- one lane's instance -----------------------------------------------------
 
+// Compensated summation (FP32 only): the FP32 kernels carry the rounding
+// error of every update y <- y + h sum_j b_j k_j in yc and add it to the next
+// update (Kahan's compensation, with the exact error of the sum taken by
+// Knuth's branch-free TwoSum), so a long solve does not accumulate one
+// float rounding of y per step; the stage inputs and the error estimate
+// keep plain float arithmetic.
+template <typename R>
+constexpr bool kCompensated = std::is_same<R, float>::value;
+
 template <typename R, int N>
 struct Lane {
   R y[N];
+  R yc[N];  // compensation of y (FP32), zero in FP64
   R k[7][N];
   // next_te is the instance's next evaluation time, next_te2 the one after:
   // it is fetched one emission early, so an emission never waits on memory.
@@ -135,10 +145,12 @@ __device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<
       L.cursor + 1 < a.E ? a.t_eval[(long)i * a.E + L.cursor + 1] : INFINITY;
   const R* yr = s.y + (long)i * a.D;
   const R* kr = s.k1 + (long)i * a.D;
+  const R* cr = s.yc + (long)i * a.D;
 #pragma unroll
   for (int q = 0; q < N; ++q) {
     L.y[q] = q < L.dim ? yr[q] : R(0);
     L.k[0][q] = q < L.dim ? kr[q] : R(0);
+    L.yc[q] = (kCompensated<R> && q < L.dim) ? cr[q] : R(0);
   }
 }
 
@@ -159,6 +171,7 @@ __device__ __forceinline__ void store_lane(const AnalyticArgs<R>& a, const Lane<
   s.prev_rej[i] = L.prev_rej;
   write_row<R, N>(s.y + (long)i * a.D, a.D, L.y, L.dim);
   write_row<R, N>(s.k1 + (long)i * a.D, a.D, L.k[0], L.dim);
+  if (kCompensated<R>) write_row<R, N>(s.yc + (long)i * a.D, a.D, L.yc, L.dim);
 }
 
 // Writes the final state, and NaN for evaluation times never reached.
@@ -190,7 +203,10 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
 
   // Stages 2..7: Y_s = y + h sum_{j<s} a_sj k_j, k_s = f(t + c_s h, Y_s).
   // (The fields here are autonomous, so the stage time is not formed.)
-  R Y[N];
+  // The last stage input is the new solution (SSAL); in FP32 it is the
+  // compensated sum of y and the update plus the carried error, whose new
+  // rounding error goes to Yc.
+  R Y[N], Yc[N];
 #pragma unroll
   for (int s = 1; s < 7; ++s) {
 #pragma unroll
@@ -199,7 +215,16 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
 #pragma unroll
       for (int j = 0; j < s; ++j)
         if (M::A[s][j] != 0.0) acc += R(M::A[s][j]) * L.k[j][q];
-      Y[q] = L.y[q] + hs * acc;
+      if (kCompensated<R> && s == 6) {
+        const R inc = hs * acc + L.yc[q];
+        const R sum = L.y[q] + inc;
+        const R bv = sum - L.y[q];
+        const R av = sum - bv;
+        Yc[q] = (L.y[q] - av) + (inc - bv);
+        Y[q] = sum;
+      } else {
+        Y[q] = L.y[q] + hs * acc;
+      }
     }
     f(Y, L.k[s]);
   }
@@ -226,9 +251,11 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
   constexpr bool kSq = std::is_same<R, float>::value;
   const R err = kSq ? err2 : ctl_sqrt(err2);
   const bool accept = a.ctrl.fixed || err < R(1);
-  if (REC && L.n_att <= a.rec_cap)
-    a.h_rec[(long)L.inst * a.rec_cap + L.n_att - 1] =
-        accept ? double(hs) : -double(hs);
+  if (REC && L.n_att <= a.rec_cap) {
+    const long o = (long)L.inst * a.rec_cap + L.n_att - 1;
+    a.h_rec[o] = accept ? double(hs) : -double(hs);
+    a.e_rec[o] = kSq ? sqrt(double(err)) : double(err);  // FP32: err holds err^2
+  }
 
   // Controller: on acceptance
   // clamp(safety err^-beta1 err_prev^beta2 err_prev2^beta3), capped at 1
@@ -278,7 +305,7 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
 #pragma unroll
         for (int j = 0; j < 7; ++j)
           if (dense_uses<M>(j)) s2 += w[j] * L.k[j][q];
-        out[q] = L.y[q] + hs * s2;
+        out[q] = L.y[q] + (kCompensated<R> ? hs * s2 + L.yc[q] : hs * s2);
       }
       write_row_n<R, N>(a.y_eval + ((long)L.inst * a.E + L.cursor) * a.D,
                         a.D, out, L.dim);
@@ -322,6 +349,7 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       L.y[q] = Y[q];
+      if (kCompensated<R>) L.yc[q] = Yc[q];
       L.k[0][q] = L.k[6][q];  // FSAL
     }
   }
@@ -471,7 +499,10 @@ __device__ __forceinline__ void init_one(const AnalyticArgs<R>& a, int i) {
   L.atol = R(a.atol[i]);
   const R* y0 = a.y0 + (long)i * a.D;
 #pragma unroll
-  for (int q = 0; q < N; ++q) L.y[q] = q < L.dim ? y0[q] : R(0);
+  for (int q = 0; q < N; ++q) {
+    L.y[q] = q < L.dim ? y0[q] : R(0);
+    L.yc[q] = R(0);
+  }
   f(L.y, L.k[0]);
   L.n_fe = 1;
   L.n_att = L.n_acc = L.n_rej = 0;

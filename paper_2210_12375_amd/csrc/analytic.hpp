@@ -36,6 +36,7 @@ struct AnalyticArgs {
   int32_t* list;
   int32_t* counts;
   double* h_rec;  // [B, rec_cap] attempted step sizes (rejected < 0)
+  double* e_rec;  // [B, rec_cap] their error norms
   int32_t rec_cap;
   DenseKeep<R> dk;
   int32_t keep_dense;

@@ -46,6 +46,10 @@ struct State {
   int32_t* prev_rej; // last attempt was rejected
   R* y;              // [B, D] current state
   R* k1;             // [B, D] f(t, y) (first stage, FSAL)
+  // [B, D] FP32 analytic kernels: the rounding error of the last update
+  // y <- y + h sum b_j k_j (compensated summation), carried into the next
+  // update and the dense outputs; unused (may be null) elsewhere
+  R* yc;
 };
 
 // Interpolant of each instance's last accepted step, kept on request so

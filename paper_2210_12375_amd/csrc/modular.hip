@@ -53,6 +53,7 @@ struct Mod {
   int32_t* last;   // [B] the current attempt ends on t_end
   R* aux;          // [B] start-step scratch
   double* h_rec;   // [B, rec_cap] attempt record (rejected < 0)
+  double* e_rec;   // [B, rec_cap] the attempts' error norms
   int32_t rec_cap;
   int32_t* n_running;
   DenseKeep<R> dk;
@@ -487,9 +488,11 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
   const R err = ctl_sqrt(ctl_div(acc, R(D)));
   const bool accept = m.ctrl.fixed || err < R(1);
   const int n_att = m.st.n_att[row] + 1;
-  if (lane == 0 && m.h_rec != nullptr && n_att <= m.rec_cap)
+  if (lane == 0 && m.h_rec != nullptr && n_att <= m.rec_cap) {
     m.h_rec[(long)row * m.rec_cap + n_att - 1] =
         accept ? double(hs) : -double(hs);
+    m.e_rec[(long)row * m.rec_cap + n_att - 1] = double(err);
+  }
   const Ctrl& c = m.ctrl;
   const R pw = ctl_pow(err, accept ? R(-c.beta1) : R(-0.2));
   R fac = R(c.safety) * pw;
@@ -786,6 +789,7 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
   R* aux = L.take<R>(B);
   int32_t* nrun = L.take<int32_t>(64);
   double* h_rec = c.record_cap > 0 ? L.take<double>(B * c.record_cap) : nullptr;
+  double* e_rec = c.record_cap > 0 ? L.take<double>(B * c.record_cap) : nullptr;
   DenseKeep<R> dk{};
   if (c.keep_dense) {
     dk.t_prev = L.take<double>(B);
@@ -850,6 +854,7 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     m->aux = aux;
     m->n_running = nrun;
     m->h_rec = h_rec;
+    m->e_rec = e_rec;
     m->rec_cap = c.record_cap;
     m->dk = dk;
     m->keep = c.keep_dense;
@@ -1119,6 +1124,7 @@ hipError_t modular_init(ModularPlan& mp, const bode_config& c,
     mp.cursor = m.st.cursor;
     mp.prev_rej = m.st.prev_rej;
     mp.h_rec = m.h_rec;
+    mp.e_rec = m.e_rec;
     mp.n_running = m.n_running;
   };
   if (im->is64) {

@@ -25,6 +25,7 @@ struct ModularPlan {
           *n_fe = nullptr, *status = nullptr, *cursor = nullptr,
           *prev_rej = nullptr;
   double* h_rec = nullptr;
+  double* e_rec = nullptr;
   int32_t* n_running = nullptr;  // device counter (1 int) in the workspace
   void* impl = nullptr;          // kernel-side plan (owned)
 };

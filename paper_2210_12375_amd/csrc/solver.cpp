@@ -185,9 +185,11 @@ size_t layout_analytic(const bode_config& c, void* base,
   st.prev_rej = L.take<int32_t>(B);
   st.y = L.take<R>(B * D);
   st.k1 = L.take<R>(B * D);
+  st.yc = c.joint ? nullptr : L.take<R>(B * D);
   int32_t* list = L.take<int32_t>(B);
   int32_t* cnt = L.take<int32_t>(8);
   double* h_rec = c.record_cap > 0 ? L.take<double>(B * c.record_cap) : nullptr;
+  double* e_rec = c.record_cap > 0 ? L.take<double>(B * c.record_cap) : nullptr;
   bode::DenseKeep<R> dk{};
   if (c.keep_dense) {
     dk.t_prev = L.take<double>(B);
@@ -210,6 +212,7 @@ size_t layout_analytic(const bode_config& c, void* base,
     a->list = list;
     a->counts = cnt;
     a->h_rec = h_rec;
+    a->e_rec = e_rec;
     a->rec_cap = c.record_cap;
     a->dk = dk;
     a->keep_dense = c.keep_dense;
@@ -709,6 +712,27 @@ int solver_get_steps(const bode_solver* cs, double* h, int32_t* n) {
     return BODE_OK;
   } catch (...) {
     return fail(s, BODE_EHIP, "unknown error in solver_get_steps");
+  }
+}
+
+int solver_get_errors(const bode_solver* cs, double* err) {
+  bode_solver* s = const_cast<bode_solver*>(cs);
+  try {
+    if (!s) return fail(nullptr, BODE_EINVAL, "solver is NULL");
+    if (!err) return fail(s, BODE_EINVAL, "err is NULL");
+    if (s->cfg.record_cap < 1)
+      return fail(s, BODE_ESTATE,
+                  "error norms are recorded only if record_cap > 0");
+    const double* src =
+        s->cfg.rhs != BODE_RHS_ANALYTIC ? s->mp.e_rec
+                                        : (is64(s->cfg) ? s->ad.e_rec
+                                                        : s->af.e_rec);
+    HIP_TRY(hipMemcpyAsync(err, src,
+                           sizeof(double) * s->cfg.B * s->cfg.record_cap,
+                           hipMemcpyDeviceToDevice, s->stream));
+    return BODE_OK;
+  } catch (...) {
+    return fail(s, BODE_EHIP, "unknown error in solver_get_errors");
   }
 }
 

@@ -56,6 +56,7 @@ def run_gpu(p, method="dopri5", precision="fp64", rhs=bd.RHS_ANALYTIC, **kw):
         h, n = s.steps()
         out["h_rec"] = h.cpu().numpy()
         out["n_rec"] = n.cpu().numpy()
+        out["e_rec"] = s.errors().cpu().numpy()
     torch.cuda.synchronize()
     return out, s
 
@@ -165,6 +166,9 @@ def replay_check(p, g, method, ctrl=None, tol=TOL_FP64, decisions=True,
     cap = int(max(1, n[idx].max()))
     Hs = H[idx, :cap]
     fin = (g["status"][idx] == 1).astype(np.int32)
+    if "e_rec" in g:  # the record's own decisions and controller steps
+        controller_record_check(q, Hs, g["e_rec"][idx, :cap], n[idx], ctrl,
+                                "fp64")
     rr = oracle.solve(q, method=method, h_replay=Hs, n_replay=n[idx],
                       replay_errors=True, replay_final=fin, **kw)
     np.testing.assert_array_equal(rr["status"] == 1, fin == 1)
@@ -275,3 +279,224 @@ def assert_linear_accuracy(p, g, n_max=64, factor=50.0):
         ref = expm(A * (p["t_end"][i] - p["t0"][i])) @ p["y0"][i]
         bound = factor * (p["rtol"][i] * np.abs(ref).max() + p["atol"][i])
         assert np.abs(g["y_final"][i] - ref).max() <= bound, i
+
+
+# Relative agreement of a recorded step size with the controller law applied
+# to the recorded error norms.  FP64: pow and products correctly rounded to a
+# few ulps.  FP32 / BF16: the exponent of the factor is formed in float from
+# terms up to ~60 in magnitude (log2 of squared norms) and the hardware
+# log2 / exp2 are ~1 ulp, so the factor carries ~1e-6 relative rounding;
+# 1e-5 leaves a margin of ten.
+CTL_RTOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-5}
+
+
+def controller_record_check(p, h_rec, e_rec, n, ctrl=None, precision="fp64",
+                            fixed=False):
+    """The GPU's step record against its own recorded error norms and the
+    controller law declared in include/batchode.h (paper section 3: each
+    instance accepts or rejects on its own error norm and sizes its next step
+    from its own error history; appendix C for the PID family):
+      - an attempt is accepted exactly when its recorded norm is below 1
+        (every attempt in fixed-step mode);
+      - the next attempt's size is hs * fac, fac the law of the header
+        evaluated in FP64 on the recorded norms (err_prev, err_prev2 the
+        norms of the two previous accepted attempts clamped below at 1e-4, 1
+        before any), clipped to t_end - t when t + hs * fac reaches t_end,
+        within CTL_RTOL[precision].
+    Returns the number of checked proposals."""
+    c = dict(beta1=0.14, beta2=0.08, beta3=0.0, safety=0.9, fac_min=0.2,
+             fac_max=10.0)
+    c.update(ctrl or {})
+    B, cap = h_rec.shape
+    n = np.minimum(n, cap)
+    k_idx = np.arange(cap)[None, :]
+    valid = k_idx < n[:, None]
+    acc = h_rec > 0
+    if fixed:
+        assert np.all(acc[valid]), "a fixed-step attempt was rejected"
+    else:
+        dec = e_rec < 1.0
+        wrong = valid & (acc != dec)
+        assert not wrong.any(), (np.argwhere(wrong)[:5], e_rec[wrong][:5])
+    rtol = CTL_RTOL[precision]
+    t = np.asarray(p["t0"], np.float64).copy()
+    te = np.asarray(p["t_end"], np.float64)
+    ep1 = np.ones(B)
+    ep2 = np.ones(B)
+    prev_rej = np.zeros(B, bool)
+    checked = 0
+    for k in range(cap - 1):
+        live = n > k + 1
+        if not live.any():
+            break
+        hk = np.abs(h_rec[:, k])
+        e = e_rec[:, k]
+        a = acc[:, k]
+        with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+            fa = (c["safety"] * e ** -c["beta1"] * ep1 ** c["beta2"]
+                  * ep2 ** c["beta3"])
+            fr = c["safety"] * e ** -0.2
+        fa = np.where(e == 0.0, c["fac_max"], fa)
+        fa = np.clip(fa, c["fac_min"], c["fac_max"])
+        fa = np.where(prev_rej, np.minimum(1.0, fa), fa)
+        fr = np.maximum(c["fac_min"], fr)
+        fac = np.where(a, fa, fr)
+        fac = np.where(np.isfinite(e), fac, c["fac_min"])
+        if fixed:
+            fac = np.ones(B)
+        t = np.where(a, t + hk, t)
+        ep2 = np.where(a, ep1, ep2)
+        ep1 = np.where(a, np.maximum(e, 1e-4), ep1)
+        prev_rej = ~a
+        with np.errstate(invalid="ignore"):  # attempts past n are unset
+            prop = hk * fac
+        clip = t + prop >= te
+        expect = np.where(clip, te - t, prop)
+        ambiguous = np.abs(t + prop - te) <= 10 * rtol * prop
+        chk = live & ~ambiguous
+        nxt = np.abs(h_rec[:, k + 1])
+        bad = chk & (np.abs(nxt - expect) > rtol * expect)
+        assert not bad.any(), (k, np.flatnonzero(bad)[:5], nxt[bad][:5],
+                               expect[bad][:5])
+        checked += int(chk.sum())
+    return checked
+
+
+# FP32 phase allowance of the analytic replay check, as a fraction of the
+# time an output lies after t0: 2^-20, eight float ulps of the elapsed time.
+# The FP32 state is rounded to float at every stage; on the slow branch of a
+# stiff relaxation oscillation (Van der Pol, mu up to 20) a state
+# perturbation dy moves the phase by about mu dy, and at the fast jump that
+# follows a phase error dt moves the state by |y'| dt ~ mu dt, so float
+# rounding alone gives errors up to ~mu^2 eps_f32 ~ 1e-4 at outputs that
+# fall inside a jump while the final state agrees to ~1e-7.  Such an output
+# counts as agreeing when it is within tol of the oracle's solution at a time
+# at most 2^-20 (t_e - t0) away: |a - b| <= tol scale + 2^-20 (t_e - t0) |f|.
+PHASE_REL = 2.0 ** -20
+
+
+def phase_allowance(p, kinds_ok, r_eval, diff_eval, bound):
+    """For outputs of analytic instances whose difference exceeds bound
+    (per instance), the phase allowance 2^-20 (t_e - t0) max |f(t_e, b)|
+    with f evaluated by the oracle at its own output b; zero elsewhere."""
+    B, E = diff_eval.shape
+    allow = np.zeros((B, E))
+    for i, e in zip(*np.nonzero(diff_eval > bound[:, None])):
+        if not kinds_ok[i]:
+            continue
+        dim = int(p["dim"][i])
+        te = p["t_eval"][i, e]
+        f = oracle.rhs(p, i, te, r_eval[i, e, :dim])
+        allow[i, e] = PHASE_REL * (te - p["t0"][i]) * np.abs(f).max()
+    return allow
+
+
+def reduced_replay_check(p, g, method, precision, ctrl=None,
+                         decision_band=None, decision_kinds=(0, 1, 2, 3),
+                         tol=None, phase=False):
+    """Reduced-precision (FP32 / BF16) solve against the FP64 oracle, attempt
+    by attempt:
+      - controller_record_check: every decision equals its own recorded norm
+        test and every next step size is the controller law applied to the
+        recorded norms (CTL_RTOL);
+      - the oracle replays the recorded attempts in FP64 on the inputs the
+        GPU received (state-typed inputs rounded to float); every instance's
+        outputs agree within tol (1e-4 FP32, 1e-2 BF16) of the instance's
+        scale, the largest magnitude among its outputs and its initial
+        state (an instance that decays far below its start is measured
+        against where it started);
+      - if decision_band is given, every decision of the kinds in
+        decision_kinds agrees with the oracle's FP64 norm test, except
+        near-ties |err - 1| <= decision_band.
+    Returns the per-instance relative errors and the attempts' recorded and
+    oracle norms."""
+    tol = tol if tol is not None else (TOL_BF16 if precision == "bf16"
+                                       else TOL_FP32)
+    kw = ctrl or {}
+    n = g["n_rec"]
+    H, E = g["h_rec"], g["e_rec"]
+    assert n.max() <= H.shape[1], "record_cap too small"
+    checked = controller_record_check(p, H, E, n, ctrl, precision)
+    q = as_float_inputs(p)
+    cap = int(max(1, n.max()))
+    fin = (g["status"] == bd.SUCCESS).astype(np.int32)
+    rr = oracle.solve(q, method=method, h_replay=H[:, :cap], n_replay=n,
+                      replay_errors=True, replay_final=fin, **kw)
+    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], rr["y_eval"],
+                                       rr["y_final"])
+    scale = np.maximum(scale, np.abs(q["y0"]).max(axis=1))
+    rel = diff / np.maximum(scale, 1e-300)
+    n_phase = 0
+    if phase and rel.max() > tol:
+        B = scale.size
+        de = np.abs(np.nan_to_num(g["y_eval"]) - np.nan_to_num(rr["y_eval"]))
+        de = de.reshape(B, g["y_eval"].shape[1], -1).max(axis=2)
+        df = np.abs(np.nan_to_num(g["y_final"]) - np.nan_to_num(rr["y_final"]))
+        df = df.max(axis=1)
+        bound = tol * scale
+        allow = phase_allowance(q, q["kind"] <= 1, rr["y_eval"], de, bound)
+        n_phase = int(np.sum((de > bound[:, None]) & (de <= bound[:, None]
+                                                      + allow)))
+        bad = np.flatnonzero((de > bound[:, None] + allow).any(axis=1)
+                             | (df > bound))
+        assert bad.size == 0, (bad[:5], rel[bad[:5]])
+    else:
+        worst = int(np.argmax(rel))
+        assert rel.max() <= tol, (worst, rel[worst], int(n[worst]))
+    valid = np.arange(cap)[None, :] < n[:, None]
+    eo, eg = rr["err_rec"], E[:, :cap]
+    if decision_band is not None:
+        dk = np.isin(q["kind"], decision_kinds)[:, None]
+        acc = H[:, :cap] > 0
+        wrong = (valid & dk & (acc != (eo < 1.0))
+                 & (np.abs(eo - 1.0) > decision_band))
+        assert not wrong.any(), (np.argwhere(wrong)[:5], eo[wrong][:5],
+                                 eg[wrong][:5])
+    return dict(rel=rel, e_gpu=eg, e_oracle=eo, valid=valid,
+                n_ctl_checked=checked, n_phase=n_phase)
+
+
+def norm_bias(info, kinds, kind, lo=0.1, hi=10.0):
+    """Median relative deviation of the recorded norms from the oracle's over
+    the attempts of one kind whose oracle norm lies in [lo, hi] (the norms
+    that decide steps)."""
+    eo, eg, v = info["e_oracle"], info["e_gpu"], info["valid"]
+    m = v & (kinds[:, None] == kind) & (eo >= lo) & (eo <= hi)
+    if not m.any():
+        return 0.0
+    return float(np.median(np.abs(eg[m] - eo[m]) / eo[m]))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def grad_errors(p, g, dy0, dth):
+    """Relative L2 errors of every parameter tensor (W1 ... b3) separately
+    and of every instance's dy0 row, so a wrong small block (a bias, the
+    time row of W1, one instance) cannot hide under the norm of the whole
+    vector."""
+    errs, off = {}, 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        size = np.asarray(p["mlp"][k]).size
+        errs[k] = rel_l2(g["dth"][off:off + size], dth[off:off + size])
+        off += size
+    assert off == dth.size
+    n_in = np.asarray(p["mlp"]["W1"]).shape[0]  # the time row is the last
+    W1g = g["dth"][:np.asarray(p["mlp"]["W1"]).size].reshape(n_in, -1)
+    W1r = dth[:W1g.size].reshape(n_in, -1)
+    errs["W1_time_row"] = rel_l2(W1g[-1], W1r[-1])
+    rows = np.linalg.norm(g["dy0"] - dy0, axis=1) / np.maximum(
+        np.linalg.norm(dy0, axis=1), 1e-300)
+    errs["dy0_rows"] = float(rows.max())
+    errs["dy0"] = rel_l2(g["dy0"], dy0)
+    errs["dtheta"] = rel_l2(g["dth"], dth)
+    return errs
+
+
+def assert_grads(p, g, dy0, dth, tol):
+    errs = grad_errors(p, g, dy0, dth)
+    print("  " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+    return errs

@@ -2,8 +2,10 @@
 against the FP64 oracle, through the C ABI.
 
 FP64 mode: identical per-instance accepted / rejected / evaluation counts and
-statuses, outputs within 1e-9 relative per instance.  FP32 mode: the oracle
-replays the GPU's accepted steps in FP64, outputs within 1e-4 relative.
+statuses, outputs within 1e-9 relative per instance.  FP32 mode: every decision
+and step size of the GPU's attempt record follows from its recorded error
+norms by the controller law, and the oracle's FP64 replay of the record agrees
+within 1e-4 relative per instance.
 """
 import numpy as np
 import pytest
@@ -12,9 +14,9 @@ import torch
 import oracle
 from gpu_helpers import (TOL_FP32, as_float_inputs, assert_fp64_parity,
                          assert_linear_accuracy,
-                         assert_uneven_parity, controller, oracle_replay,
-                         per_instance_absdiff, per_instance_rel, replay_check,
-                         run_gpu)
+                         assert_uneven_parity, controller, norm_bias,
+                         oracle_replay, per_instance_absdiff, per_instance_rel,
+                         reduced_replay_check, replay_check, run_gpu)
 from paper_2210_12375_amd import binding as bd
 from paper_2210_12375_amd import workloads as W
 
@@ -77,54 +79,92 @@ def test_uneven_fp64_parity_ragged(method):
     assert_linear_accuracy(p, g)
 
 
+# Bound on the median relative deviation of the FP32 error norms from the
+# FP64 oracle's on the same steps, over the attempts whose norm decides
+# (0.1 <= err <= 10).  A unit norm at rtol = 1e-6 is an estimate
+# h sum_j e_j k_j of about 1e-6 |y| formed from terms h e_j k_j of up to
+# |e_j| |y| (sum_j e_j = 0 cancels them), each rounded to float, so the norm
+# carries relative noise up to eps_f32 / rtol * sum_j |e_j| = 0.06 sum |e_j|
+# (Dormand-Prince sum |e_j| = 0.16, Tsitouras 1.21); the bound is
+# 0.1 sum_j |e_j|.  A wrong coefficient, scale or dimension shifts the
+# median by O(1).  Checked
+# on the Van der Pol attempts: the linear family's steps sit on the
+# stability boundary, where its norm is rounding noise of the decayed stiff
+# modes in either precision.
+def norm_bias_bound(method):
+    return 0.1 * np.abs(bd.solver_tableau(method)[3]).sum()
+
+
+def check_uneven_fp32(p, g, method, ctrl=None):
+    info = reduced_replay_check(p, g, method, "fp32", ctrl, phase=True)
+    rel = info["rel"]
+    b = norm_bias(info, p["kind"], W.VDP)
+    assert b <= norm_bias_bound(method), b
+    flush(f"  max rel {rel.max():.2e} (p99 {np.quantile(rel, 0.99):.2e}, "
+          f"{info['n_phase']} outputs within the phase allowance), "
+          f"proposals checked {info['n_ctl_checked']}, norm bias VdP "
+          f"{norm_bias(info, p['kind'], W.VDP):.1e} linear "
+          f"{norm_bias(info, p['kind'], W.LINEAR):.1e}")
+    return info
+
+
 @pytest.mark.parametrize("method", METHODS)
 def test_uneven_fp32_replay_parity(method):
-    """FP32 state, norm and controller: the oracle replays the GPU's attempt
-    record in FP64.  At least 99 % of instances must agree within 1e-4 of
-    their scale, and every instance within the larger of 1e-4 and what its
-    trajectory's amplification of rounding allows:
-
-    * 10 x its FP64 amplification (the oracle's plain and contracted builds
-      differ by up to ~2000 ulps on the same steps for long stiff runs) at
-      float's unit roundoff;
-    * for Van der Pol instances, 30 x the deviation of an oracle replay that
-      rounds the state to float after every accepted step.  That probe makes
-      one float-sized perturbation per step; the GPU makes several (each
-      stage input is rounded and stiff stages multiply it by h |J| = O(1)),
-      and a phase error of a relaxation oscillation persists, so the long
-      stiff runs drift by up to ~1e-3.  The probe is not used for the linear
-      family: replayed at its stability boundary without the controller's
-      feedback, injected perturbations grow."""
+    """FP32 state, norm and controller (compensated summation of the state
+    update): every decision and every proposed step size of the GPU's record
+    follows from its recorded error norms by the controller law; the FP64
+    oracle's replay of that record agrees within 1e-4 for every instance;
+    the recorded norms agree with the oracle's without bias."""
     flush(f"uneven fp32 replay {method}")
     p = W.uneven_batch(B=1024)
     g, _ = run_gpu(p, method=method, precision="fp32", record_cap=4096)
     assert np.all(g["status"] == bd.SUCCESS)
-    p = as_float_inputs(p)  # the oracle solves the inputs the GPU received
-    r = oracle_replay(p, g, method)
-    n = g["n_rec"]
-    h = g["h_rec"][:, :n.max()]
-    rf = oracle.solve(p, method=method, h_replay=h, n_replay=n, variant="fma")
-    rp = oracle.solve(p, method=method, h_replay=h, n_replay=n,
-                      round_state_f32=True)
-    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
-                                       r["y_final"])
-    sens, _ = per_instance_absdiff(rf["y_eval"], rf["y_final"], r["y_eval"],
-                                   r["y_final"])
-    probe, _ = per_instance_absdiff(rp["y_eval"], rp["y_final"], r["y_eval"],
-                                    r["y_final"])
-    # relative to the instance's scale: its outputs or, for instances that
-    # decay far below their start, its initial state
-    scale = np.maximum(scale, np.abs(p["y0"]).max(axis=1))
-    amp = sens / scale / np.finfo(np.float64).eps
-    allowed = np.maximum(TOL_FP32, 10.0 * amp * np.finfo(np.float32).eps)
-    vdp = p["kind"] == W.VDP
-    allowed[vdp] = np.maximum(allowed[vdp], 30.0 * probe[vdp] / scale[vdp])
-    rel = diff / scale
-    worst = np.argmax(rel / allowed)
-    assert np.all(rel <= allowed), (worst, rel[worst], allowed[worst])
-    assert np.mean(rel <= TOL_FP32) >= 0.99, np.mean(rel <= TOL_FP32)
-    flush(f"  within 1e-4: {np.mean(rel <= TOL_FP32):.4f}, max {rel.max():.2e}"
-          f", worst/allowed {rel[worst] / allowed[worst]:.2f}")
+    check_uneven_fp32(p, g, method)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_headline_fp32_full_batch_sampled(method):
+    """The benchmark's workload itself: all 65,536 instances of the uneven
+    batch in FP32 with the step record, 2048 sampled instances checked
+    attempt by attempt as above; the whole batch's outputs are bitwise those
+    of the solve without the record (the benchmark's launch configuration)."""
+    flush(f"uneven full 65536 fp32 {method}")
+    p = W.uneven_batch()
+    g, _ = run_gpu(p, method=method, precision="fp32", record_cap=2048)
+    assert np.all(g["status"] == bd.SUCCESS)
+    assert g["n_rec"].max() <= 2048
+    plain, _ = run_gpu(p, method=method, precision="fp32")
+    np.testing.assert_array_equal(plain["y_final"], g["y_final"])
+    np.testing.assert_array_equal(plain["y_eval"], g["y_eval"])
+    np.testing.assert_array_equal(plain["n_accepted"], g["n_accepted"])
+    idx = np.random.default_rng(2048).choice(p["y0"].shape[0], 2048,
+                                             replace=False)
+    check_uneven_fp32(W.subset(p, idx), {k: v[idx] for k, v in g.items()},
+                      method)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_fp32_decisions_accuracy_limited(method):
+    """Non-stiff Van der Pol (mu <= 2) and slowly decaying linear instances
+    (rates <= 1) over short spans, where every step is accuracy-limited:
+    every FP32 accept / reject decision equals the FP64 oracle's on the same
+    step, except near-ties |err - 1| <= 2 eps_f32 / rtol * sum_j |e_j| (the
+    float noise of the norm, see norm_bias_bound: 0.019 Dormand-Prince,
+    0.145 Tsitouras at rtol 1e-6)."""
+    flush(f"fp32 decisions, accuracy-limited {method}")
+    p = W.uneven_batch(B=2000)
+    p["mu"] = np.minimum(p["mu"], 2.0)
+    p["A"] = p["A"] * 0.1
+    p["t_end"] = p["t_end"] / 5.0
+    p["t_eval"] = p["t_eval"] / 5.0
+    g, _ = run_gpu(p, method=method, precision="fp32", record_cap=4096)
+    assert np.all(g["status"] == bd.SUCCESS)
+    band = 2.0 * np.finfo(np.float32).eps / 1e-6 * np.abs(
+        bd.solver_tableau(method)[3]).sum()
+    assert np.all(p["rtol"] == 1e-6)
+    info = reduced_replay_check(p, g, method, "fp32", decision_band=band)
+    flush(f"  max rel {info['rel'].max():.2e}, norm bias VdP "
+          f"{norm_bias(info, p['kind'], W.VDP):.1e}")
 
 
 @pytest.mark.parametrize("method", METHODS)
@@ -271,11 +311,8 @@ def test_pid_fp32_replay(ctrl):
     g, _ = run_gpu(p, method="dopri5", precision="fp32", record_cap=4096, **c)
     assert np.all(g["status"] == bd.SUCCESS)
     q = as_float_inputs(p)
-    r = oracle_replay(q, g, "dopri5")
-    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
-                                       r["y_final"])
-    rel = diff / np.maximum(scale, np.abs(q["y0"]).max(axis=1))
-    assert np.mean(rel <= TOL_FP32) >= 0.99, np.sort(rel)[-5:]
+    info = reduced_replay_check(p, g, "dopri5", "fp32", c)
+    flush(f"  max rel {info['rel'].max():.2e}")
     f = oracle.solve(q, method="dopri5", **c)
     flush(f"  steps {g['n_accepted'].mean():.1f} vs FP64 "
           f"{f['n_accepted'].mean():.1f}")

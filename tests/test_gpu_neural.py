@@ -3,10 +3,14 @@ C ABI.
 
 FP64 mode (FMA field kernel): identical counts and statuses and outputs
 within 1e-9 of the free-running FP64 oracle, plus the decision-by-decision
-replay check.  FP32 mode: the oracle replays the GPU's attempt record on the
-float-rounded inputs, 1e-4.  BF16 mode (MFMA, split-BF16 activations, BF16
-weights): the same replay, 1e-2 (the stated bound for a BF16 right-hand
-side); step counts reported against FP64.
+replay check.  FP32 mode: every decision and step size of the GPU's attempt
+record follows from its recorded error norms by the controller law, every
+decision equals the FP64 oracle's on the same step (near-ties within 0.05
+aside), and the oracle's replay of the record on the float-rounded inputs
+agrees within 1e-4.  BF16 mode (MFMA, split-BF16 activations, BF16 weights):
+the same checks, outputs within 1e-2 (the stated bound for a BF16
+right-hand side) and near-ties within 0.5 (the field itself differs by the
+weights' BF16 rounding); step counts reported against FP64.
 """
 import numpy as np
 import pytest
@@ -14,7 +18,8 @@ import pytest
 import oracle
 from gpu_helpers import (TOL_BF16, TOL_FP32, as_float_inputs,
                          assert_fp64_parity, oracle_replay,
-                         per_instance_absdiff, replay_check, run_gpu)
+                         per_instance_absdiff, reduced_replay_check,
+                         replay_check, run_gpu)
 from paper_2210_12375_amd import binding as bd
 from paper_2210_12375_amd import workloads as W
 
@@ -25,12 +30,20 @@ def flush(msg):
     print(msg, flush=True)
 
 
-def replay_rel(p, g, method):
-    q = as_float_inputs(p)
-    r = oracle_replay(q, g, method)
-    diff, scale = per_instance_absdiff(g["y_eval"], g["y_final"], r["y_eval"],
-                                       r["y_final"])
-    return diff / np.maximum(scale, 1e-300)
+# Near-tie bands of the reduced-precision decision checks: FP32 norms carry
+# float rounding of the cancelling estimate, about eps_f32 / rtol *
+# sum |e_j| < 1e-2 at the neural tolerances (rtol 1e-5); in BF16 the field is
+# evaluated with BF16-rounded weights, a fixed perturbation of relative size
+# 2^-9 per weight that moves the estimate of its fifth-order error term by a
+# few tenths at most.
+DECISION_BAND = {"fp32": 0.05, "bf16": 0.5}
+
+
+def replay_rel(p, g, method, precision):
+    """Attempt-by-attempt check of a reduced-precision record; returns the
+    per-instance relative errors of the oracle's replay."""
+    return reduced_replay_check(p, g, method, precision,
+                                decision_band=DECISION_BAND[precision])["rel"]
 
 
 @pytest.mark.parametrize("method", ["dopri5", "tsit5"])
@@ -76,7 +89,7 @@ def test_mlp_reduced_precision_replay(precision, tol):
     g, _ = run_gpu(p, method="dopri5", precision=precision, rhs=bd.RHS_MLP,
                    record_cap=256)
     assert np.all(g["status"] == bd.SUCCESS)
-    rel = replay_rel(p, g, "dopri5")
+    rel = replay_rel(p, g, "dopri5", precision)
     assert rel.max() <= tol, (rel.max(), np.argmax(rel))
     r = oracle.solve(p, method="dopri5")
     infl = g["n_accepted"].mean() / r["n_accepted"].mean()
@@ -95,7 +108,7 @@ def test_mlp_bf16_full_size_sampled():
     assert np.all(g["status"] == bd.SUCCESS)
     idx = np.random.default_rng(5).choice(p["y0"].shape[0], 64, replace=False)
     rel = replay_rel(W.subset(p, idx), {k: v[idx] for k, v in g.items()},
-                     "dopri5")
+                     "dopri5", "bf16")
     assert rel.max() <= TOL_BF16, rel.max()
     np.testing.assert_array_equal(g["n_attempted"],
                                   g["n_accepted"] + g["n_rejected"])
@@ -119,7 +132,7 @@ def test_cnf_reduced_precision_replay(precision, tol):
     g, _ = run_gpu(p, method="tsit5", precision=precision, rhs=bd.RHS_CNF,
                    record_cap=256)
     assert np.all(g["status"] == bd.SUCCESS)
-    rel = replay_rel(p, g, "tsit5")
+    rel = replay_rel(p, g, "tsit5", precision)
     assert rel.max() <= tol, (rel.max(), np.argmax(rel))
 
 
@@ -131,7 +144,7 @@ def test_cnf_bf16_full_size_sampled():
     assert np.all(g["status"] == bd.SUCCESS)
     idx = np.random.default_rng(6).choice(p["y0"].shape[0], 32, replace=False)
     rel = replay_rel(W.subset(p, idx), {k: v[idx] for k, v in g.items()},
-                     "dopri5")
+                     "dopri5", "bf16")
     assert rel.max() <= TOL_BF16, rel.max()
 
 
@@ -155,7 +168,7 @@ def test_field_kernel_shapes(precision, d, hidden, cnf):
     g, _ = run_gpu(p, method=method, precision=precision, rhs=rhs,
                    record_cap=256)
     assert np.all(g["status"] == bd.SUCCESS)
-    rel = replay_rel(p, g, method)
+    rel = replay_rel(p, g, method, precision)
     tol = TOL_FP32 if precision == "fp32" else TOL_BF16
     flush(f"  max rel {rel.max():.2e}")
     assert rel.max() <= tol, (rel.max(), np.argmax(rel))
