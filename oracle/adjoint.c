@@ -333,7 +333,9 @@ int orc_adjoint(const orc_problem* P, const orc_options* O,
   const long np = (P->W1 ? n_params(P) : 0);
   const int nt = O->n_threads > 0 ? O->n_threads : omp_get_max_threads();
   double* part = calloc((size_t)(np > 0 ? np : 1) * nt, sizeof(double));
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  /* contiguous blocks of instances per thread, partial sums added in thread
+   * order: the same sum order on every run with the same thread count */
+#pragma omp parallel for schedule(static) num_threads(nt)
   for (int32_t i = 0; i < P->B; ++i) {
     grads G = split(P, part + (long)omp_get_thread_num() * (np > 0 ? np : 1));
     adjoint_one(P, O, i, h_steps, n_steps, cap, g_eval, g_final, dy0, G);

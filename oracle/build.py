@@ -17,9 +17,19 @@ LIB = os.path.join(HERE, "liboracle.so")
 LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
 
 
-def _build_one(out, contract, verbose):
+# The same source built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (any report aborts), for a CPU test that runs the oracle's entry points
+# under them; loaded only by that test, with the sanitizer runtimes
+# preloaded.
+LIB_SAN = os.path.join(HERE, "liboracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer", "-g"]
+
+
+def _build_one(out, contract, verbose, extra=()):
     cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", f"-ffp-contract={contract}",
            "-fPIC", "-Wall", "-Wextra", "-shared", "-o", out + ".tmp"]
+    cmd[1:1] = list(extra)
     if contract == "fast":
         cmd.insert(3, "-mfma")
     cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
@@ -33,6 +43,11 @@ def build(verbose: bool = False) -> str:
     _build_one(LIB, "off", verbose)
     _build_one(LIB_FMA, "fast", verbose)
     return LIB
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    _build_one(LIB_SAN, "off", verbose, SAN_FLAGS)
+    return LIB_SAN
 
 
 def needs_build() -> bool:

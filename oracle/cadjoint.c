@@ -345,7 +345,9 @@ int orc_cadjoint(const orc_problem* P, const orc_options* O, int32_t joint,
 
   const int nt = O->n_threads > 0 ? O->n_threads : omp_get_max_threads();
   double* part = calloc((size_t)(p > 0 ? p : 1) * nt, sizeof(double));
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  /* contiguous blocks of instances per thread, partial sums added in thread
+   * order: the same sum order on every run with the same thread count */
+#pragma omp parallel for schedule(static) num_threads(nt)
   for (int32_t i = 0; i < B; ++i) {
     if (fwd_status[i] != ORC_SUCCESS) continue;
     const int n = P->dim[i];

@@ -57,18 +57,27 @@ class _Options(C.Structure):
                 ("beta3", C.c_double), ("fixed_step", C.c_int32)]
 
 
+_variants = {}
+
+
 def _load(variant=None):
-    global _lib, _lib_fma
-    if variant == "fma":
-        if _lib_fma is None:
-            _load()
-            lib = C.CDLL(_build.LIB_FMA)
-            lib.orc_solve.restype = C.c_int
-            lib.orc_solve.argtypes = _lib.orc_solve.argtypes
-            lib.orc_solve_joint.restype = C.c_int
-            lib.orc_solve_joint.argtypes = _lib.orc_solve.argtypes
-            _lib_fma = lib
-        return _lib_fma
+    """The oracle library; variant "fma" is the contracted build (a rounding
+    probe), "san" the sanitizer build (only under preloaded sanitizer
+    runtimes)."""
+    global _lib
+    if variant in ("fma", "san"):
+        if variant not in _variants:
+            base = _load()
+            path = _build.LIB_FMA if variant == "fma" else _build.LIB_SAN
+            lib = C.CDLL(path)
+            for name in ("orc_solve", "orc_solve_joint", "orc_adjoint",
+                         "orc_cadjoint", "orc_rhs", "orc_tableau",
+                         "orc_dense_weights", "orc_initial_step"):
+                f = getattr(lib, name)
+                f.restype = getattr(base, name).restype
+                f.argtypes = getattr(base, name).argtypes
+            _variants[variant] = lib
+        return _variants[variant]
     if _lib is None:
         if _build.needs_build():
             _build.build()
