@@ -344,9 +344,9 @@ def neural_suite(bd, W, rl, steps, warmup):
     import torch
     out = {}
 
-    def run(p, rhs, precision, backward, nsteps):
+    def run(p, rhs, precision, backward, nsteps, **extra):
         dp = bd.device_problem(p, precision)
-        opts = dict(method="dopri5", precision=precision, rhs=rhs)
+        opts = dict(method="dopri5", precision=precision, rhs=rhs, **extra)
         if backward:
             opts.update(record_cap=256, ckpt_every=2)
         P = sum(np.asarray(p["mlp"][k]).size
@@ -376,8 +376,20 @@ def neural_suite(bd, W, rl, steps, warmup):
         d = p["y0"].shape[1] - (1 if rhs == bd.RHS_CNF else 0)
         H = p["mlp"]["W1"].shape[1]
         evals = (2 + 6 * rounds) * p["y0"].shape[0]  # rows the kernels touch
-        fl = evals * rl.mlp_flops_per_row(d, H) * (2 if rhs == bd.RHS_CNF else 1)
-        r = dict(ms=ms, accepted=acc, steps_mean=float(st["n_accepted"].mean()),
+        row = rl.mlp_flops_per_row(d, H) * (2 if rhs == bd.RHS_CNF else 1)
+        fl = evals * row
+        if backward:
+            # per accepted step and stage: the vector-Jacobian product and
+            # the parameter-gradient outer products, each one field's worth
+            # of multiply-adds (the recomputation of checkpointed stages is
+            # not counted)
+            fl += acc * 7 * 2 * row
+        na = st["n_accepted"]
+        r = dict(ms=ms, accepted=acc, steps_mean=float(na.mean()),
+                 steps_p50=float(np.median(na)),
+                 steps_p90=float(np.quantile(na, 0.9)), steps_max=int(na.max()),
+                 steps_hist={int(k): int(v) for k, v in
+                             zip(*np.unique(na, return_counts=True))},
                  rounds=rounds, ok=bool(np.all(st["status"] == 1)),
                  model_tflops=fl / (ms * 1e-3) / 1e12)
         if backward:
@@ -388,6 +400,8 @@ def neural_suite(bd, W, rl, steps, warmup):
 
     p3 = W.neural_ode()
     out["neural_fwd_4096_bf16"] = run(p3, bd.RHS_MLP, "bf16", False, steps)
+    out["neural_fwd_4096_bf16_plain"] = run(p3, bd.RHS_MLP, "bf16", False,
+                                            steps, plain_bf16=1)
     out["neural_fwd_4096_fp64"] = run(p3, bd.RHS_MLP, "fp64", False,
                                       max(1, steps // 2))
     p4 = W.neural_ode_fit()

@@ -137,6 +137,14 @@ typedef struct {
                          clipped to end there; the error estimate is not
                          used.  Not with joint mode or solver_cadjoint.
                          0: adaptive (the controller above).                */
+  int32_t plain_bf16; /* BF16 mode with MLP / CNF fields: 1 rounds every
+                         activation to one BF16 value (8 significant bits;
+                         one MFMA per fragment, a third of the matrix-core
+                         work); 0 (default) splits it into three BF16 terms
+                         (24 bits), so the only BF16 rounding is that of
+                         the weights.  Plain BF16 is built for forward
+                         solves: solver_backward and solver_cadjoint return
+                         BODE_EUNSUPPORTED for it.                           */
 } bode_config;
 
 /* Problem description: device pointers (NULL where not used). */

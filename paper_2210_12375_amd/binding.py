@@ -53,7 +53,7 @@ class Config(C.Structure):
                 ("tune_block", C.c_int32), ("tune_lanes", C.c_int32),
                 ("ckpt_every", C.c_int32), ("beta3", C.c_double),
                 ("joint", C.c_int32), ("eager", C.c_int32),
-                ("fixed_step", C.c_int32)]
+                ("fixed_step", C.c_int32), ("plain_bf16", C.c_int32)]
 
 
 _PROBLEM_FIELDS = ["y0", "t0", "t_end", "rtol", "atol", "t_eval", "h0", "kind",
@@ -134,7 +134,7 @@ def make_config(B, D, E=0, method="dopri5", precision="fp64",
                 beta2=PI_CONTROLLER["beta2"], safety=0.9, fac_min=0.2,
                 fac_max=10.0, record_cap=0, keep_dense=0, mlp_hidden=0,
                 tune_block=0, tune_lanes=0, ckpt_every=0, beta3=0.0,
-                joint=0, eager=0, fixed_step=0):
+                joint=0, eager=0, fixed_step=0, plain_bf16=0):
     c = Config()
     c.method = METHODS[method] if isinstance(method, str) else method
     c.precision = (PRECISIONS[precision] if isinstance(precision, str)
@@ -149,6 +149,7 @@ def make_config(B, D, E=0, method="dopri5", precision="fp64",
     c.joint = joint
     c.eager = eager
     c.fixed_step = fixed_step
+    c.plain_bf16 = plain_bf16
     return c
 
 

@@ -106,8 +106,29 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   if (tid < PR && r0 + tid < B && a.act[r0 + tid] == kRunning)
     any_running = 1;
   __syncthreads();
-  if (!any_running) return;
   const long kb = a.kb;
+  if (!any_running) {
+    // no row of the tile has this step: its cotangent rows of the tape are
+    // zero (the gradient GEMMs read every row; a tape holds several steps,
+    // so these rows may hold an earlier step's values)
+    for (int idx = tid; idx < PR * H; idx += blockDim.x) {
+      const int r = idx / H, c = idx % H, row = r0 + r;
+      if (row >= B) continue;
+      a.T1g[(kb + row) * H + c] = 0.f;
+      a.T2g[(kb + row) * H + c] = 0.f;
+      if (CNF) {
+        a.T1g[(kb + B + row) * H + c] = 0.f;
+        a.T2g[(kb + B + row) * H + c] = 0.f;
+      }
+    }
+    for (int idx = tid; idx < PR * din; idx += blockDim.x) {
+      const int r = idx / din, c = idx % din, row = r0 + r;
+      if (row >= B) continue;
+      a.T3g[(kb + row) * din + c] = 0.f;
+      if (CNF) a.T3g[(kb + B + row) * din + c] = 0.f;
+    }
+    return;
+  }
   const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
   auto on = [&](int row) { return row < B && a.act[row] == kRunning; };
 
@@ -422,7 +443,7 @@ MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
 }
 
 hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s) {
-  if (a.w.packedT == nullptr) return hipErrorInvalidValue;
+  if (a.w.packedT == nullptr || a.w.plain) return hipErrorInvalidValue;
   if (a.w.f32)
     return a.cnf ? vjp_h<F32, true>(a, s) : vjp_h<F32, false>(a, s);
   return a.cnf ? vjp_h<Bf3, true>(a, s) : vjp_h<Bf3, false>(a, s);
@@ -432,6 +453,8 @@ hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s) {
   (void)row_tile;
   if (a.w.f32)
     return a.cnf ? field_h<F32, true>(a, s) : field_h<F32, false>(a, s);
+  if (a.w.plain)
+    return a.cnf ? field_h<Bf1, true>(a, s) : field_h<Bf1, false>(a, s);
   return a.cnf ? field_h<Bf3, true>(a, s) : field_h<Bf3, false>(a, s);
 }
 

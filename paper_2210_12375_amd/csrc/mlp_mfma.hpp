@@ -19,6 +19,9 @@ struct MfmaWeights {
   // W3^T, W2^T and W1^T without its time row (null when not needed).
   void* packedT = nullptr;
   int f32 = 0;
+  // BF16 mode: 1 rounds every activation to one BF16 term (plain BF16);
+  // 0 splits it into three (hi + mid + lo, FP32's precision).
+  int plain = 0;
 };
 
 size_t mfma_packed_bytes(int din, int H, int f32);

@@ -171,6 +171,45 @@ struct Bf3 {
   }
 };
 
+// Plain BF16 policy: the same BF16 weights, but every activation rounded
+// once to the nearest BF16 value (8 significant bits) and one MFMA per
+// fragment: a third of Bf3's matrix-core work, at the price of activation
+// rounding of relative size 2^-9 in every layer.
+struct Bf1 {
+  typedef uint16_t W;
+  typedef uint16_t A;
+  static constexpr int kPlanes = 1, kPad = 8;
+  __device__ static __forceinline__ void put(A* p, int, int off, float v) {
+    p[off] = f2bf(v);
+  }
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
+                                              const A* Ah, int, int lda,
+                                              const W* Bp, int nk, int nn,
+                                              int nb0, int nstep, int ntiles,
+                                              int lane) {
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    for (int kb = 0; kb < nk; ++kb) {
+      bf16x8 ah[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        ah[mt] = lds8(Ah + (mt * 16 + r) * lda + kb * 32 + kq);
+      bf16x8 bfrag[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t)
+        if (t < ntiles)
+          bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 +
+                                lane) * 8);
+#pragma unroll
+      for (int t = 0; t < NTW; ++t)
+        if (t < ntiles)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
+    }
+  }
+};
+
 // FP32 policy: A and B fragments are 8 FP32 values per lane; product q of
 // a 32-wide k block takes element q of both (the 4 k indices of one
 // 16x16x4 product are kb*32 + g*8 + q, g = lane / 16).

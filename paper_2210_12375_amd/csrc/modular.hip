@@ -105,18 +105,36 @@ struct Back {
   R* yseg;         // [k + 1, B, D] states of the current segment
   R* slots;        // [G, P] split-K partials of the parameter gradient
   int32_t* flags;  // [0]: max accepted steps, [1]: record overflow
-  // Tape of one step, sample-major ([k][feature], k = stage * Bs + row,
-  // Bs = B, or 2B for the CNF whose tangent rows follow the primal ones):
+  // Tape of C steps, sample-major ([k][feature], k = (slot * 7 + stage) *
+  // Bs + row, Bs = B, or 2B for the CNF whose tangent rows follow the
+  // primal ones; slot = the step's place in its chunk of C):
   // layer inputs with a trailing constant feature (1 on primal rows, 0 on
   // tangent rows: the bias gradient) and the layer-output cotangents.  Row
   // widths: T1in din + 2, T2in and T3in H + 1, T1g and T2g H, T3g din.
   R *T1in, *T1g, *T2in, *T2g, *T3in, *T3g;
-  long K;  // 7 * Bs
-  int32_t cap, k, G;
+  long K;  // 7 * Bs * C
+  int32_t cap, k, G, C;
   long P;
 };
 
 constexpr int kSlots = 128;  // most k-splits of a parameter-gradient GEMM
+
+// Steps per chunk of the discrete adjoint's gradient tape: the parameter
+// gradient is one GEMM per layer over a whole chunk, so a small batch's
+// GEMMs run on enough tape rows to fill the chip (one step of a
+// 1024-instance MLP is 7168 rows, 0.9 GFLOP); at most 8 steps and at most
+// 512 MiB of tape (a 8192-instance CNF step alone is ~1 GB: one step).
+inline int tape_steps(const bode_config& c, long B, int din, int H,
+                      size_t elem) {
+  const long rows = 7L * B * (c.rhs == BODE_RHS_CNF ? 2 : 1);
+  const size_t per_step =
+      (size_t)rows * (size_t)((din + 2) + H + 2 * (H + 1) + H + din) * elem;
+  const size_t budget = size_t(512) << 20;
+  int steps = per_step > 0 ? (int)(budget / per_step) : 1;
+  if (steps > 8) steps = 8;
+  if (steps > c.record_cap) steps = c.record_cap;
+  return steps < 1 ? 1 : steps;
+}
 
 inline long n_params(int din, int H) {
   const long n0 = din + 1;
@@ -675,10 +693,13 @@ hipError_t fused_h(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
 
 template <class M>
 hipError_t fused_launch(const Mod<float>& m, const FusedArgs& f, int f32,
-                        hipStream_t s) {
+                        int plain, hipStream_t s) {
   if (f32)
     return m.cnf ? fused_h<mtile::F32, true, M>(m, f, s)
                  : fused_h<mtile::F32, false, M>(m, f, s);
+  if (plain)
+    return m.cnf ? fused_h<mtile::Bf1, true, M>(m, f, s)
+                 : fused_h<mtile::Bf1, false, M>(m, f, s);
   return m.cnf ? fused_h<mtile::Bf3, true, M>(m, f, s)
                : fused_h<mtile::Bf3, false, M>(m, f, s);
 }
@@ -828,7 +849,8 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     bk.slots = L.take<R>((size_t)bk.G * bk.P);
     bk.flags = L.take<int32_t>(64);
     const int H = c.mlp_hidden, n0 = din + 1;
-    bk.K = 7L * (long)B * (c.rhs == BODE_RHS_CNF ? 2 : 1);
+    bk.C = tape_steps(c, B, din, H, sizeof(R));
+    bk.K = 7L * (long)B * (c.rhs == BODE_RHS_CNF ? 2 : 1) * bk.C;
     bk.T1in = L.take<R>((size_t)(n0 + 1) * bk.K);
     bk.T1g = L.take<R>((size_t)H * bk.K);
     bk.T2in = L.take<R>((size_t)(H + 1) * bk.K);
@@ -839,6 +861,7 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
   MfmaWeights w{};
   if (uses_mfma(c, din)) {
     w.f32 = c.precision == BODE_FP32;
+    w.plain = c.precision == BODE_BF16 && c.plain_bf16;
     w.packed = L.take<unsigned char>(mfma_packed_bytes(din, c.mlp_hidden, w.f32));
     w.fvec = L.take<float>(mfma_fvec_elems(din, c.mlp_hidden));
     // transposed layers for the VJP kernels (discrete and continuous adjoint)
@@ -942,7 +965,7 @@ hipError_t run_fused(const ModImpl& im, const Mod<float>& m, int budget,
     f.st[st - 1] = stage_args(im, m, sp, m.K + (size_t)st * m.B * m.D);
   }
   f.budget = budget;
-  return fused_launch<M>(m, f, im.mw.f32, s);
+  return fused_launch<M>(m, f, im.mw.f32, im.mw.plain, s);
 }
 
 template <typename R>
@@ -1173,6 +1196,9 @@ struct VjpSpec {
   // Continuous adjoint: mu_s = J^T kappa_s is stored here ([B, D]) and the
   // discrete adjoint's row updates are skipped.
   void* mu_out;
+  // First tape row of this step (the tape holds several steps, 7 Bs rows
+  // each; stage s starts at kbase + (s - 1) Bs).
+  long kbase;
 };
 
 template <typename R>
@@ -1402,7 +1428,7 @@ __global__ __launch_bounds__(256) void vjp_kernel(Mod<R> m, Back<R> b,
     // tape of this stage: layer inputs (+ bias feature) and cotangents
     {
       const long Bs = cnf ? 2L * B : (long)B;
-      const long kb = (long)(s - 1) * Bs;
+      const long kb = sp.kbase + (long)(s - 1) * Bs;
       const int l1 = n0 + 1, lh = H + 1;
       for (int idx = threadIdx.x; idx < ROWS * l1; idx += blockDim.x) {
         const int r = idx / l1, f = idx % l1, row = r0 + r;
@@ -1526,7 +1552,7 @@ hipError_t vjp(const ModImpl& im, const Mod<R>& m, const Back<R>& b,
       a.T3in = b.T3in;
       a.T3g = b.T3g;
       a.K = b.K;
-      a.kb = (long)(sp.s - 1) * (m.cnf ? 2L * m.B : (long)m.B);
+      a.kb = sp.kbase + (long)(sp.s - 1) * (m.cnf ? 2L * m.B : (long)m.B);
       a.s = sp.s;
       a.n = sp.n;
       for (int j = 0; j < sp.n; ++j) {
@@ -1959,19 +1985,26 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
     e = stages<R, M>(im, v, b, nullptr, true, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval);
-    {  // tape cotangents of skipped (inactive) tiles must read as zero
-      const long H = m.H;
-      hipLaunchKernelGGL(fill_r<R>, lin_grid(H * b.K), blk, 0, s, b.T1g,
-                         H * b.K, R(0));
-      hipLaunchKernelGGL(fill_r<R>, lin_grid(H * b.K), blk, 0, s, b.T2g,
-                         H * b.K, R(0));
-      hipLaunchKernelGGL(fill_r<R>, lin_grid((long)m.d_in * b.K), blk, 0, s,
-                         b.T3g, (long)m.d_in * b.K, R(0));
+    // this step's place in its tape chunk (steps are taken in reverse)
+    const int slot = (nmax - 1 - n) % b.C;
+    const long Bs = m.cnf ? 2L * m.B : (long)m.B;
+    const long kbase = (long)slot * 7 * Bs;
+    if (im.mw.packedT == nullptr) {
+      // FMA kernels skip tiles without a step n: their cotangent rows must
+      // read as zero (the matrix-core kernels write those zeros themselves)
+      const long H = m.H, rows = 7 * Bs;
+      hipLaunchKernelGGL(fill_r<R>, lin_grid(H * rows), blk, 0, s,
+                         b.T1g + kbase * H, H * rows, R(0));
+      hipLaunchKernelGGL(fill_r<R>, lin_grid(H * rows), blk, 0, s,
+                         b.T2g + kbase * H, H * rows, R(0));
+      hipLaunchKernelGGL(fill_r<R>, lin_grid((long)m.d_in * rows), blk, 0, s,
+                         b.T3g + kbase * m.d_in, (long)m.d_in * rows, R(0));
     }
     for (int st = 7; st >= 1; --st) {
       VjpSpec sp{};
       sp.s = st;
       sp.c = M::C[st - 1];
+      sp.kbase = kbase;
       // kappa_j receives h a_{s j} mu_s for the stages j < s
       const StageSpec ss = stage_spec<M>(st - 1 > 0 ? st - 1 : 0);
       sp.n = st - 1 > 0 ? ss.n : 0;
@@ -1982,16 +2015,19 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       e = vjp<R>(im, m, b, sp, s);
       if (e != hipSuccess) return e;
     }
-    {  // parameter gradient of this step
+    if (slot == b.C - 1 || n == 0) {
+      // parameter gradient of the chunk's steps: one GEMM per layer over
+      // its (slot + 1) * 7 * Bs tape rows
+      const long Kc = (long)(slot + 1) * 7 * Bs;
       const int H = m.H, din = m.d_in, n0 = din + 1;
       const long o2 = (long)(n0 + 1) * H, o3 = o2 + (long)(H + 1) * H;
-      e = launch_grad_gemm<R>(b.T1in, b.T1g, b.K, n0 + 1, H, b.G, b.slots,
+      e = launch_grad_gemm<R>(b.T1in, b.T1g, Kc, n0 + 1, H, b.G, b.slots,
                               b.P, 0, s);
       if (e == hipSuccess)
-        e = launch_grad_gemm<R>(b.T2in, b.T2g, b.K, H + 1, H, b.G, b.slots,
+        e = launch_grad_gemm<R>(b.T2in, b.T2g, Kc, H + 1, H, b.G, b.slots,
                                 b.P, o2, s);
       if (e == hipSuccess)
-        e = launch_grad_gemm<R>(b.T3in, b.T3g, b.K, H + 1, din, b.G, b.slots,
+        e = launch_grad_gemm<R>(b.T3in, b.T3g, Kc, H + 1, din, b.G, b.slots,
                                 b.P, o3, s);
       if (e != hipSuccess) return e;
     }

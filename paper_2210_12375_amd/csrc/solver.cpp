@@ -134,6 +134,8 @@ std::string check_config(const bode_config* c) {
   if (c->fixed_step != 0 && c->fixed_step != 1)
     return "fixed_step must be 0 or 1";
   if (c->eager != 0 && c->eager != 1) return "eager must be 0 or 1";
+  if (c->plain_bf16 != 0 && c->plain_bf16 != 1)
+    return "plain_bf16 must be 0 or 1";
   if (c->fixed_step && c->joint)
     return "fixed_step is not built for joint mode";
   if (c->record_cap < 0) return "record_cap must be >= 0";
@@ -603,6 +605,9 @@ int solver_backward(bode_solver* s, const void* g_y_eval,
       return fail(s, BODE_EUNSUPPORTED,
                   "backward is built for MLP and CNF fields");
     if (!dtheta) return fail(s, BODE_EINVAL, "dtheta is required");
+    if (s->cfg.precision == BODE_BF16 && s->cfg.plain_bf16)
+      return fail(s, BODE_EUNSUPPORTED,
+                  "plain BF16 is built for forward solves only");
     hipError_t e = bode::modular_backward(s->mp, g_y_eval, g_y_final, dy0,
                                           dtheta, s->stream);
     if (e == hipErrorInvalidValue)
@@ -641,6 +646,9 @@ int solver_cadjoint(bode_solver* s, int32_t joint, const void* g_y_eval,
     if (s->cfg.fixed_step)
       return fail(s, BODE_EUNSUPPORTED,
                   "the continuous adjoint is built for adaptive solves");
+    if (s->cfg.precision == BODE_BF16 && s->cfg.plain_bf16)
+      return fail(s, BODE_EUNSUPPORTED,
+                  "plain BF16 is built for forward solves only");
     if (!s->stepped) return fail(s, BODE_ESTATE, "no completed solve");
     const size_t need = bode::modular_cadjoint_bytes(s->mp, joint);
     if (workspace_bytes < need)

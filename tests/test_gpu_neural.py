@@ -284,3 +284,44 @@ def test_commit_row_widths(d):
     r = oracle.solve(p, method="dopri5")
     assert np.all(r["status"] == bd.SUCCESS)
     assert_fp64_parity(g, r)
+
+
+@pytest.mark.parametrize("rhs,keep", [(bd.RHS_MLP, 0), (bd.RHS_MLP, 1),
+                                      (bd.RHS_CNF, 0)])
+def test_plain_bf16_forward(rhs, keep):
+    """Plain BF16 activations (one BF16 term, one MFMA per fragment) in the
+    fused solve (keep = 0) and the per-stage path (keep = 1): the record's
+    decisions and step sizes follow from its norms by the controller law,
+    the oracle's replay agrees within the BF16 bound, and step counts are
+    reported beside the split-BF16 solve of the same batch.  Decisions are
+    not compared with the oracle's: every activation's rounding (relative
+    2^-9) is noise in each stage value, of the size of the embedded error
+    estimate at rtol 1e-5, so the GPU's norms are ~1 where the oracle's are
+    ~1e-6 (the step inflation the plain mode shows)."""
+    cnf = rhs == bd.RHS_CNF
+    flush(f"plain bf16 {'cnf' if cnf else 'mlp'} keep={keep}")
+    p = W.cnf_density(B=256) if cnf else W.neural_ode(B=512)
+    g, _ = run_gpu(p, method="dopri5", precision="bf16", rhs=rhs,
+                   record_cap=512, plain_bf16=1, keep_dense=keep)
+    assert np.all(g["status"] == bd.SUCCESS)
+    rel = reduced_replay_check(p, g, "dopri5", "bf16")["rel"]
+    assert rel.max() <= TOL_BF16, (rel.max(), np.argmax(rel))
+    split, _ = run_gpu(p, method="dopri5", precision="bf16", rhs=rhs)
+    flush(f"  max rel {rel.max():.2e}; accepted steps plain p50 "
+          f"{np.median(g['n_accepted'])} max {g['n_accepted'].max()}, split "
+          f"p50 {np.median(split['n_accepted'])} max "
+          f"{split['n_accepted'].max()}")
+
+
+def test_plain_bf16_refuses_backward():
+    p = W.neural_ode_fit(B=16)
+    dp = bd.device_problem(p, "bf16")
+    s = bd.Solver(dp, precision="bf16", rhs=bd.RHS_MLP, record_cap=64,
+                  ckpt_every=2, plain_bf16=1)
+    s.solve()
+    import torch
+    with pytest.raises(bd.BodeError) as ei:
+        s.backward(torch.zeros_like(s.y_eval), torch.zeros_like(s.y_final),
+                   99136)
+    assert ei.value.code == bd.EUNSUPPORTED
+    s.close()
