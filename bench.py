@@ -43,7 +43,7 @@ def parse():
                     help="skip the neural-field workloads")
     ap.add_argument("--study", default="",
                     choices=["", "cadjoint", "neural", "ceilings", "hbm",
-                             "paper"],
+                             "paper", "fwdbwd"],
                     help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
@@ -338,7 +338,7 @@ def cpu_configs(method="dopri5"):
     return out
 
 
-def neural_suite(bd, W, rl, steps, warmup):
+def neural_suite(bd, W, rl, steps, warmup, only=None):
     """The neural-field workloads: forward solves (accepted instance-steps/s)
     and forward + discrete-adjoint backward passes (fwd+bwd/s)."""
     import torch
@@ -398,6 +398,10 @@ def neural_suite(bd, W, rl, steps, warmup):
             r["instance_steps_per_s"] = acc / (ms * 1e-3)
         return r
 
+    if only == "fwdbwd":  # the 1024-instance MLP fwd+bwd workload alone
+        out["neural_fwdbwd_1024_bf16"] = run(W.neural_ode_fit(), bd.RHS_MLP,
+                                             "bf16", True, steps)
+        return out
     p3 = W.neural_ode()
     out["neural_fwd_4096_bf16"] = run(p3, bd.RHS_MLP, "bf16", False, steps)
     out["neural_fwd_4096_bf16_plain"] = run(p3, bd.RHS_MLP, "bf16", False,
@@ -601,6 +605,10 @@ def main():
         return
     if a.study == "hbm":
         print(json.dumps({"hbm_study": hbm_study(bd, W)}), flush=True)
+        return
+    if a.study == "fwdbwd":
+        print(json.dumps({"neural": neural_suite(bd, W, rl, a.steps, a.warmup,
+                                                 only="fwdbwd")}), flush=True)
         return
     if a.study == "neural":
         print(json.dumps({"neural": neural_suite(bd, W, rl, 2, 1)}),

@@ -178,8 +178,41 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   };
 
   float keep[2][NTW][4];
+  if (a.act_in != nullptr) {
+    // the forward layers as the stage's field evaluation stored them
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+      float* Tin = layer == 0 ? a.T2in : a.T3in;
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = rq + i;
+          const bool primal = !CNF || row < PR;
+          const int g = r0 + (primal ? row : row - PR);
+          // rows without this step read as zero (their stored values
+          // come from stale states)
+          const float kv =
+              g < B && a.act[g] == kRunning
+                  ? a.act_in[((long)(g + (primal ? 0 : B)) * 2 + layer) * H +
+                             n]
+                  : 0.f;
+          keep[layer][t][i] = kv;
+          float act = kv;
+          if (CNF) {
+            const float ap = __shfl_xor(kv, 32, 64);
+            if (!primal) act = (1.f - ap * ap) * kv;
+          }
+          const long k = tk(row);
+          if (k >= 0) Tin[k * (H + 1) + n] = act;
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int layer = 0; layer < 2; ++layer) {
+    if (a.act_in != nullptr) break;
     f32x4 acc[1][NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};

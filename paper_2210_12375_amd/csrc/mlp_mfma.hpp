@@ -50,6 +50,11 @@ struct MfmaArgs {
   double c;
   int write_y7;
   float* out;
+  // If not null, the hidden layers' values of every row are stored here for
+  // a later vector-Jacobian product: [Bs][2][H] (Bs = B, or 2B for the CNF
+  // whose tangent rows follow), layer 1 then layer 2 of each row; the
+  // activation on primal rows, the pre-activation tangent on tangent rows.
+  float* act_out;
 };
 
 MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
@@ -84,6 +89,10 @@ struct MfmaVjpArgs {
   // Continuous adjoint: if not null, mu_s is stored here ([B, D], zero in
   // the columns the field does not read) instead of the row updates above.
   float* mu_out;
+  // If not null, the hidden layers' values of this stage as a field kernel
+  // stored them (MfmaArgs::act_out's layout): the two forward layers are
+  // read instead of recomputed.
+  const float* act_in;
 };
 
 hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s);

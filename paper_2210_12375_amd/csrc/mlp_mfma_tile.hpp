@@ -140,6 +140,14 @@ struct Bf3 {
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
+    // the weight fragments of k block kb + 1 are requested before the
+    // products of block kb, so the L2 latency of one block overlaps the
+    // matrix work of the previous one
+    bf16x8 bfrag[NTW], bnext[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t)
+      if (t < ntiles)
+        bfrag[t] = gld8(Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8);
     for (int kb = 0; kb < nk; ++kb) {
       bf16x8 ah[MT], am[MT], al[MT];
 #pragma unroll
@@ -149,13 +157,12 @@ struct Bf3 {
         am[mt] = lds8(Ah + plane + off);
         al[mt] = lds8(Ah + 2 * plane + off);
       }
-      bf16x8 bfrag[NTW];
+      const int kn = kb + 1 < nk ? kb + 1 : kb;
 #pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        const int nb = nb0 + t * nstep;
+      for (int t = 0; t < NTW; ++t)
         if (t < ntiles)
-          bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb) * 64 + lane) * 8);
-      }
+          bnext[t] =
+              gld8(Bp + ((size_t)(kn * nn + nb0 + t * nstep) * 64 + lane) * 8);
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
         if (t < ntiles) {
@@ -167,6 +174,8 @@ struct Bf3 {
           }
         }
       }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) bfrag[t] = bnext[t];
     }
   }
 };
@@ -189,16 +198,21 @@ struct Bf1 {
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
+    bf16x8 bfrag[NTW], bnext[NTW];  // next block's weights in flight
+#pragma unroll
+    for (int t = 0; t < NTW; ++t)
+      if (t < ntiles)
+        bfrag[t] = gld8(Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8);
     for (int kb = 0; kb < nk; ++kb) {
       bf16x8 ah[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
         ah[mt] = lds8(Ah + (mt * 16 + r) * lda + kb * 32 + kq);
-      bf16x8 bfrag[NTW];
+      const int kn = kb + 1 < nk ? kb + 1 : kb;
 #pragma unroll
       for (int t = 0; t < NTW; ++t)
         if (t < ntiles)
-          bfrag[t] = gld8(Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 +
+          bnext[t] = gld8(Bp + ((size_t)(kn * nn + nb0 + t * nstep) * 64 +
                                 lane) * 8);
 #pragma unroll
       for (int t = 0; t < NTW; ++t)
@@ -206,6 +220,8 @@ struct Bf1 {
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
             acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) bfrag[t] = bnext[t];
     }
   }
 };
@@ -227,6 +243,16 @@ struct F32 {
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
+    // next k block's weight fragments in flight during this block's products
+    f32x4 b0[NTW], b1[NTW], n0[NTW], n1[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      if (t < ntiles) {
+        const W* q = Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8;
+        b0[t] = *reinterpret_cast<const f32x4*>(q);
+        b1[t] = *reinterpret_cast<const f32x4*>(q + 4);
+      }
+    }
     for (int kb = 0; kb < nk; ++kb) {
       f32x4 a0[MT], a1[MT];
 #pragma unroll
@@ -235,14 +261,14 @@ struct F32 {
         a0[mt] = *reinterpret_cast<const f32x4*>(p);
         a1[mt] = *reinterpret_cast<const f32x4*>(p + 4);
       }
-      f32x4 b0[NTW], b1[NTW];
+      const int kn = kb + 1 < nk ? kb + 1 : kb;
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
         if (t < ntiles) {
           const W* q =
-              Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) * 8;
-          b0[t] = *reinterpret_cast<const f32x4*>(q);
-          b1[t] = *reinterpret_cast<const f32x4*>(q + 4);
+              Bp + ((size_t)(kn * nn + nb0 + t * nstep) * 64 + lane) * 8;
+          n0[t] = *reinterpret_cast<const f32x4*>(q);
+          n1[t] = *reinterpret_cast<const f32x4*>(q + 4);
         }
       }
 #pragma unroll
@@ -260,6 +286,11 @@ struct F32 {
                   a1[mt][q], b1[t][q], acc[mt][t], 0, 0, 0);
           }
         }
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        b0[t] = n0[t];
+        b1[t] = n1[t];
       }
     }
   }
@@ -368,6 +399,12 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
             if (!primal) act = (1.f - ap * ap) * v;
           }
           Op::put(Ah, PA, row * SA + n, act);
+          if (a.act_out != nullptr) {
+            const int g = r0 + (primal ? row : row - PR);
+            if (g < B)
+              a.act_out[((long)(g + (primal ? 0 : B)) * 2 + layer) * H + n] =
+                  primal ? act : v;
+          }
         }
       }
     __syncthreads();

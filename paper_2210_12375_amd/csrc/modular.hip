@@ -70,6 +70,7 @@ struct StageSpec {
   double coef[6];
   double c;
   void* yout;  // if not null, the stage input Y is written here ([B, D])
+  void* act_out;  // matrix-core fields: the hidden layers' values (MfmaArgs)
 };
 
 template <class M>
@@ -114,6 +115,13 @@ struct Back {
   R *T1in, *T1g, *T2in, *T2g, *T3in, *T3g;
   long K;  // 7 * Bs * C
   int32_t cap, k, G, C;
+  // Segment store (matrix-core fields, when it fits): the stage inputs
+  // [k][7][B][D] and hidden-layer values [k][7][Bs][2][H] of every step of
+  // the current checkpoint segment, kept from its one recomputation so the
+  // vector-Jacobian products neither recompute stages nor the forward layers
+  // (null: recompute per step).
+  R* Yst;
+  float* Ast;
   long P;
 };
 
@@ -857,6 +865,13 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     bk.T2g = L.take<R>((size_t)H * bk.K);
     bk.T3in = L.take<R>((size_t)(H + 1) * bk.K);
     bk.T3g = L.take<R>((size_t)din * bk.K);
+    const size_t Bs = B * (c.rhs == BODE_RHS_CNF ? 2 : 1);
+    const size_t store = (size_t)k * 7 * (B * D * sizeof(R) + Bs * 2 * H * 4);
+    if (std::is_same<R, float>::value && uses_mfma(c, din) &&
+        store <= (size_t(2) << 30)) {
+      bk.Yst = L.take<R>((size_t)k * 7 * B * D);
+      bk.Ast = L.take<float>((size_t)k * 7 * Bs * 2 * H);
+    }
   }
   MfmaWeights w{};
   if (uses_mfma(c, din)) {
@@ -941,6 +956,7 @@ MfmaArgs stage_args(const ModImpl& im, const Mod<float>& m,
   a.write_y7 = sp.yout != nullptr;
   a.Y7 = static_cast<float*>(sp.yout);
   a.out = out;
+  a.act_out = static_cast<float*>(sp.act_out);
   return a;
 }
 
@@ -1199,6 +1215,10 @@ struct VjpSpec {
   // First tape row of this step (the tape holds several steps, 7 Bs rows
   // each; stage s starts at kbase + (s - 1) Bs).
   long kbase;
+  // Matrix-core fields with the segment store: the stage input and the
+  // stored hidden-layer values of this stage (null: Ys and recomputation).
+  const void* Y;
+  const float* act_in;
 };
 
 template <typename R>
@@ -1538,7 +1558,9 @@ hipError_t vjp(const ModImpl& im, const Mod<R>& m, const Back<R>& b,
       a.H = m.H;
       a.cnf = m.cnf;
       a.act = b.act;
-      a.Y = b.Ys + (long)(sp.s - 1) * m.B * m.D;
+      a.Y = sp.Y != nullptr ? static_cast<const float*>(sp.Y)
+                            : b.Ys + (long)(sp.s - 1) * m.B * m.D;
+      a.act_in = sp.act_in;
       a.kap_s = b.kap + (long)(sp.s - 1) * m.B * m.D;
       a.eps = m.eps;
       a.bh = b.bh;
@@ -1933,6 +1955,24 @@ hipError_t stages(ModImpl& im, Mod<R> v, Back<R>& b, R* y7dst, bool keep_y,
   return e;
 }
 
+// One step's seven stages for the segment store: stage inputs into
+// Yst[j][s] (stage 1's, y_n itself, is copied there by adj_setup) and the
+// hidden-layer values into Ast[j][s]; stage 7's input is y_{n+1}.
+template <typename R, class M>
+hipError_t stages_store(ModImpl& im, Mod<R> v, Back<R>& b, int j,
+                        hipStream_t s) {
+  const size_t BD = (size_t)v.B * v.D;
+  const size_t AH = (size_t)v.B * (v.cnf ? 2 : 1) * 2 * v.H;
+  hipError_t e = hipSuccess;
+  for (int st = 0; st < 7 && e == hipSuccess; ++st) {
+    StageSpec sp = st == 0 ? StageSpec{} : stage_spec<M>(st);
+    sp.yout = st == 0 ? nullptr : b.Yst + ((size_t)j * 7 + st) * BD;
+    sp.act_out = b.Ast + ((size_t)j * 7 + st) * AH;
+    e = field<R>(im, v, sp, b.Ks + (size_t)st * BD, s);
+  }
+  return e;
+}
+
 template <typename R, class M>
 hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
                       const R* g_final, R* dy0, R* dtheta, hipStream_t s) {
@@ -1963,27 +2003,51 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   v.st.status = b.act;
   v.K = b.Ks;
   const int k = b.k;
+  const bool store = b.Yst != nullptr;
   for (int n = nmax - 1; n >= 0; --n) {
     const int seg = n / k, base = seg * k;
-    if (n == nmax - 1 || n == base + k - 1) {
-      // entering a segment from above: states y_base .. y_n by recomputation
-      hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b, seg,
-                         b.yseg);
-      for (int mm = base; mm < n; ++mm) {
-        R* ym = b.yseg + (size_t)(mm - base) * BD;
-        hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
-                           (const R*)nullptr, (R*)nullptr);
-        v.st.y = ym;
-        e = stages<R, M>(im, v, b, ym + BD, false, s);
-        if (e != hipSuccess) return e;
+    if (store) {
+      if (n == nmax - 1 || n == base + k - 1) {
+        // entering a segment from above: each of its steps base .. n is
+        // evaluated once, its stage inputs and layer values kept
+        hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b,
+                           seg, b.yseg);
+        const size_t BD7 = 7 * (size_t)BD;
+        for (int mm = base; mm <= n; ++mm) {
+          const int j = mm - base;
+          // y_mm: the checkpoint, else stage 7's input of step mm - 1
+          R* ym = j == 0 ? b.yseg : b.Yst + (size_t)(j - 1) * BD7 + 6 * BD;
+          hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
+                             (const R*)ym, b.Yst + (size_t)j * BD7);
+          v.st.y = ym;
+          e = stages_store<R, M>(im, v, b, j, s);
+          if (e != hipSuccess) return e;
+        }
       }
+      hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
+                         (const R*)nullptr, (R*)nullptr);
+    } else {
+      if (n == nmax - 1 || n == base + k - 1) {
+        // entering a segment from above: states y_base .. y_n by
+        // recomputation
+        hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b,
+                           seg, b.yseg);
+        for (int mm = base; mm < n; ++mm) {
+          R* ym = b.yseg + (size_t)(mm - base) * BD;
+          hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
+                             (const R*)nullptr, (R*)nullptr);
+          v.st.y = ym;
+          e = stages<R, M>(im, v, b, ym + BD, false, s);
+          if (e != hipSuccess) return e;
+        }
+      }
+      R* yn = b.yseg + (size_t)(n - base) * BD;
+      hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
+                         (const R*)yn, b.Ys);
+      v.st.y = yn;
+      e = stages<R, M>(im, v, b, nullptr, true, s);
+      if (e != hipSuccess) return e;
     }
-    R* yn = b.yseg + (size_t)(n - base) * BD;
-    hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n, (const R*)yn,
-                       b.Ys);
-    v.st.y = yn;
-    e = stages<R, M>(im, v, b, nullptr, true, s);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval);
     // this step's place in its tape chunk (steps are taken in reverse)
     const int slot = (nmax - 1 - n) % b.C;
@@ -2005,6 +2069,12 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       sp.s = st;
       sp.c = M::C[st - 1];
       sp.kbase = kbase;
+      if (store) {
+        const int j = n - base;
+        sp.Y = b.Yst + ((size_t)j * 7 + st - 1) * BD;
+        sp.act_in = b.Ast + ((size_t)j * 7 + st - 1) *
+                                ((size_t)m.B * (m.cnf ? 2 : 1) * 2 * m.H);
+      }
       // kappa_j receives h a_{s j} mu_s for the stages j < s
       const StageSpec ss = stage_spec<M>(st - 1 > 0 ? st - 1 : 0);
       sp.n = st - 1 > 0 ? ss.n : 0;
