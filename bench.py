@@ -38,7 +38,9 @@ def parse():
                     help="'all' or 'headline' (skip the side variants)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time the library's default launch shapes instead "
+                         "of the autotuned ones")
     ap.add_argument("--no-neural", action="store_true",
                     help="skip the neural-field workloads")
     ap.add_argument("--study", default="",
@@ -86,6 +88,7 @@ def timed_solves(bd, dp, method, precision, steps, warmup, autotune=False,
         torch.cuda.synchronize()
     s.close()
     cfg, prob = s.cfg, s.prob
+    shape = bd.solver_get_tune(cfg)
     ws_ptr, ws_bytes = s.workspace.data_ptr(), s.workspace.numel()
     stream = torch.cuda.current_stream()
     L = bd.lib()
@@ -123,7 +126,7 @@ def timed_solves(bd, dp, method, precision, steps, warmup, autotune=False,
     y_eval = s.y_eval.double().cpu().numpy()
     y_final = s.y_final.double().cpu().numpy()
     s.close()
-    return wall, solve_ms, st, y_eval, y_final
+    return wall, solve_ms, st, y_eval, y_final, shape
 
 
 def error_at_tolerance(p, y_eval, y_final, ref, idx):
@@ -498,7 +501,7 @@ def paper_loop_study(bd, W, steps=50, warmup=5):
     for precision in ("fp32", "fp64"):
         dp = bd.device_problem(p, precision)
         for joint in (0, 1):
-            wall, solve_ms, st, _, _ = timed_solves(
+            wall, solve_ms, st, _, _, _ = timed_solves(
                 bd, dp, "dopri5", precision, steps, warmup, joint=joint,
                 **bd.I_CONTROLLER)
             loop = int(st["n_attempted"].max())
@@ -636,7 +639,7 @@ def main():
     results = {}
     for (m, pr) in variants:
         dp = bd.device_problem(p, pr)
-        wall, solve_ms, st, ye, yf = timed_solves(
+        wall, solve_ms, st, ye, yf, shape = timed_solves(
             bd, dp, m, pr, a.steps if (m, pr) == variants[0] else
             max(3, a.steps // 2), a.warmup, autotune=a.autotune)
         acc = int(st["n_accepted"].sum())
@@ -650,11 +653,11 @@ def main():
             # the critical path: the instance with the most attempts, alone
             top = int(np.argmax(st["n_attempted"]))
             dq = bd.device_problem(W.subset(p, [top]), pr)
-            _, one_ms, _, _, _ = timed_solves(bd, dq, m, pr, 5, 2)
+            _, one_ms, _, _, _, _ = timed_solves(bd, dq, m, pr, 5, 2)
             crit = dict(instance=top, attempts=int(st["n_attempted"][top]),
                         alone_ms=float(np.median(one_ms)))
         results[(m, pr)] = dict(
-            crit=crit,
+            crit=crit, launch_shape=shape,
             ms_per_step=wall, solve_ms=solve_avg, accepted=acc,
             attempted=att, value=acc / (wall * 1e-3),
             flops=flops, ok=bool(np.all(st["status"] == 1)),
@@ -691,7 +694,10 @@ def main():
                                "times, rtol 1e-6 atol 1e-8, PI controller",
                    "method": variants[0][0], "precision": variants[0][1],
                    "instances": B, "parallelism": "1 GPU, instances over "
-                                                  "lanes"},
+                                                  "lanes",
+                   "launch_shape": dict(head["launch_shape"],
+                                        source="autotuned" if a.autotune
+                                        else "library default")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": (measured_traffic()
@@ -716,7 +722,8 @@ def main():
         "variants": {f"{m}/{pr}": {k: r[k] for k in
                                    ("value", "ms_per_step", "solve_ms",
                                     "accepted", "attempted", "steps_p50",
-                                    "steps_max", "steps_hist", "ok")}
+                                    "steps_max", "steps_hist", "ok",
+                                    "launch_shape")}
                      for (m, pr), r in results.items()},
     }
     if not a.no_neural:

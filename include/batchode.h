@@ -290,9 +290,24 @@ int solver_get_errors(const bode_solver* s, double* err);
 
 /* Times launch candidates for this configuration on the caller's problem
  * (outputs are overwritten) and keeps the fastest for later solver_init
- * calls with the same shape.  Synchronous.                                  */
+ * calls with the same shape: device architecture, right-hand side,
+ * precision, method, B, D, E, hidden width and plain_bf16.  Candidates:
+ * analytic fields, threads per workgroup {64, 128, 256} x lanes launched
+ * {B, B/2, B/4}; matrix-core neural fields, wavefronts per 16-row tile
+ * {4, 8}; the per-stage neural path, rounds per captured graph {4, 8, 16}.
+ * All candidates give bitwise the same results.  If the environment
+ * variable BATCHODE_TUNE_CACHE names a file, the kept shapes are read from
+ * it on first use and the file is rewritten after every autotune (one JSON
+ * object per line).  Synchronous.  (A performance tool, not a step of the
+ * paper's method.)                                                        */
 int solver_autotune(const bode_config* cfg, const bode_problem* p,
                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* The launch shape solver_init would use for cfg on the current device:
+ * shape[5] (host int32) = threads per workgroup, lanes for Van der Pol and
+ * for linear instances (analytic fields), wavefronts per tile and rounds
+ * per graph (neural fields); 0 means the library default.               */
+int solver_get_tune(const bode_config* cfg, int32_t* shape);
 
 /* Releases the host handle (no device memory is owned). */
 void solver_destroy(bode_solver* s);

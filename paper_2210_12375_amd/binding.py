@@ -39,7 +39,7 @@ EXPORTED = ["solver_workspace_size", "solver_init", "solver_step",
             "solver_cadjoint_workspace_bytes", "solver_cadjoint",
             "solver_get_stats", "solver_get_steps", "solver_autotune",
             "solver_destroy", "solver_last_error", "solver_tableau",
-            "solver_solve_noalloc", "solver_get_errors"]
+            "solver_solve_noalloc", "solver_get_errors", "solver_get_tune"]
 
 
 class Config(C.Structure):
@@ -106,6 +106,8 @@ def lib():
         L.solver_get_stats.argtypes = [vp, ip, ip, ip, ip, ip]
         L.solver_get_steps.restype = C.c_int
         L.solver_get_steps.argtypes = [vp, dp, ip]
+        L.solver_get_tune.restype = C.c_int
+        L.solver_get_tune.argtypes = [cp, vp]
         L.solver_get_errors.restype = C.c_int
         L.solver_get_errors.argtypes = [vp, dp]
         L.solver_autotune.restype = C.c_int
@@ -218,6 +220,16 @@ def solver_get_errors(h, err_ptr):
 def solver_autotune(cfg, prob, workspace_ptr, workspace_bytes, stream_ptr):
     _check(lib().solver_autotune(C.byref(cfg), C.byref(prob), workspace_ptr,
                                  workspace_bytes, stream_ptr))
+
+
+TUNE_FIELDS = ("block", "lanes_vdp", "lanes_lin", "waves", "rounds")
+
+
+def solver_get_tune(cfg):
+    """The launch shape solver_init would use for cfg (0: default)."""
+    out = (C.c_int32 * 5)()
+    _check(lib().solver_get_tune(C.byref(cfg), C.cast(out, C.c_void_p)))
+    return dict(zip(TUNE_FIELDS, list(out)))
 
 
 def solver_destroy(h):

@@ -402,11 +402,17 @@ hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
 // instances), while its VJP is faster on 8.
 template <class Op, bool CNF>
 hipError_t field_h(const MfmaArgs& a, hipStream_t s) {
+  const int wv = mfma_waves(a.H, CNF, a.waves);
   switch (a.H) {
     case 512:
-      return CNF ? launch_t<Op, 8, CNF, 4>(a, s) : launch_t<Op, 4, CNF, 8>(a, s);
-    case 256: return launch_t<Op, 2, CNF, 8>(a, s);
-    case 128: return launch_t<Op, 1, CNF, 8>(a, s);
+      return wv == 4 ? launch_t<Op, 8, CNF, 4>(a, s)
+                     : launch_t<Op, 4, CNF, 8>(a, s);
+    case 256:
+      return wv == 4 ? launch_t<Op, 4, CNF, 4>(a, s)
+                     : launch_t<Op, 2, CNF, 8>(a, s);
+    case 128:
+      return wv == 4 ? launch_t<Op, 2, CNF, 4>(a, s)
+                     : launch_t<Op, 1, CNF, 8>(a, s);
     default: return launch_t<Op, 1, CNF, 4>(a, s);
   }
 }
@@ -433,6 +439,15 @@ size_t mfma_packedT_bytes(int din, int H, int f32) {
 }
 
 size_t mfma_fvec_elems(int din, int H) { return 3 * (size_t)H + din; }
+
+int mfma_waves(int H, bool cnf, int requested) {
+  if (H <= 64) return 4;  // one 16-column tile per wavefront at most
+  if (requested == 4 || requested == 8) return requested;
+  // measured defaults: 8 wavefronts (two per SIMD) from width 128 up,
+  // except the CNF at width 512 (its tangent rows double the epilogue
+  // registers; 62 vs 75 us per stage evaluation of 8192 instances on 4)
+  return (cnf && H == 512) ? 4 : 8;
+}
 
 std::string mfma_supported(int din, int H) {
   if (din < 16 || din % 16 != 0 || din > 256)

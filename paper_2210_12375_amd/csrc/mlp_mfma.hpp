@@ -28,6 +28,9 @@ size_t mfma_packed_bytes(int din, int H, int f32);
 size_t mfma_packedT_bytes(int din, int H, int f32);
 size_t mfma_fvec_elems(int din, int H);
 std::string mfma_supported(int din, int H);
+// Wavefronts per 16-row tile the field kernels use: `requested` (4 or 8)
+// where the width allows it, else the default for the shape.
+int mfma_waves(int H, bool cnf, int requested);
 
 hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
                              const float* W1, const float* b1, const float* W2,
@@ -55,6 +58,8 @@ struct MfmaArgs {
   // whose tangent rows follow), layer 1 then layer 2 of each row; the
   // activation on primal rows, the pre-activation tangent on tangent rows.
   float* act_out;
+  // wavefronts per 16-row tile: 4 or 8 (0: the default for the width)
+  int waves;
 };
 
 MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,

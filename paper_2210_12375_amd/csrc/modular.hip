@@ -689,12 +689,17 @@ hipError_t fused_t(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
 // H = 512: 2.89 vs 3.35 ms per solve of 8192 instances).
 template <class Op, bool CNF, class M>
 hipError_t fused_h(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
+  const int wv = mfma_waves(m.H, CNF, f.st[0].waves);
   switch (m.H) {
     case 512:
-      return CNF ? fused_t<Op, 8, CNF, 4, M>(m, f, s)
-                 : fused_t<Op, 4, CNF, 8, M>(m, f, s);
-    case 256: return fused_t<Op, 2, CNF, 8, M>(m, f, s);
-    case 128: return fused_t<Op, 1, CNF, 8, M>(m, f, s);
+      return wv == 4 ? fused_t<Op, 8, CNF, 4, M>(m, f, s)
+                     : fused_t<Op, 4, CNF, 8, M>(m, f, s);
+    case 256:
+      return wv == 4 ? fused_t<Op, 4, CNF, 4, M>(m, f, s)
+                     : fused_t<Op, 2, CNF, 8, M>(m, f, s);
+    case 128:
+      return wv == 4 ? fused_t<Op, 2, CNF, 4, M>(m, f, s)
+                     : fused_t<Op, 1, CNF, 8, M>(m, f, s);
     default: return fused_t<Op, 1, CNF, 4, M>(m, f, s);
   }
 }
@@ -740,8 +745,9 @@ struct ModImpl {
   MfmaWeights mw{};  // packed weights of the matrix-core kernels
   bool is64 = false;
   int32_t* host_running = nullptr;  // pinned
-  // kRoundsPerSync rounds of the per-stage loop, captured once per handle
+  // rounds_per_sync rounds of the per-stage loop, captured once per handle
   hipGraphExec_t rounds_exec = nullptr;
+  int rounds_per_sync = 0;
   // private stream for captures (the caller's may be the null stream,
   // which cannot be captured; graphs are replayed on the caller's)
   hipStream_t cap_stream = nullptr;
@@ -957,6 +963,7 @@ MfmaArgs stage_args(const ModImpl& im, const Mod<float>& m,
   a.Y7 = static_cast<float*>(sp.yout);
   a.out = out;
   a.act_out = static_cast<float*>(sp.act_out);
+  a.waves = get_tune(im.cfg).waves;
   return a;
 }
 
@@ -964,8 +971,7 @@ template <>
 hipError_t field<float>(ModImpl& im, const Mod<float>& m, const StageSpec& sp,
                         float* out, hipStream_t s) {
   if (im.mw.packed != nullptr)
-    return launch_field_mfma(stage_args(im, m, sp, out), get_row_tile(im.cfg),
-                             s);
+    return launch_field_mfma(stage_args(im, m, sp, out), 0, s);
   return launch_field_fma<float>(m, sp, out, s);
 }
 
@@ -1070,17 +1076,22 @@ hipError_t run_rounds(ModImpl& im, Mod<R>& m, int budget, hipStream_t s) {
     }
     return hipSuccess;
   };
+  // rounds per running-count read-back (and per captured graph): tuned,
+  // else kRoundsPerSync; fixed for the handle once its graph is captured
+  if (im.rounds_per_sync == 0) {
+    const int t = get_tune(im.cfg).rounds;
+    im.rounds_per_sync = t > 0 ? t : kRoundsPerSync;
+  }
+  const int K = im.rounds_per_sync;
   int done = 0;
   while (done < budget) {
-    const int chunk = budget - done < kRoundsPerSync ? budget - done
-                                                     : kRoundsPerSync;
+    const int chunk = budget - done < K ? budget - done : K;
     hipError_t e;
-    if (chunk == kRoundsPerSync && !im.cfg.eager) {
+    if (chunk == K && !im.cfg.eager) {
       // a full block of rounds: one graph launch (captured on first use)
       e = im.rounds_exec != nullptr
               ? hipSuccess
-              : capture(im,
-                        [&](hipStream_t q) { return rounds(kRoundsPerSync, q); },
+              : capture(im, [&](hipStream_t q) { return rounds(K, q); },
                         &im.rounds_exec);
       if (e == hipSuccess) e = hipGraphLaunch(im.rounds_exec, s);
     } else {

@@ -52,10 +52,20 @@ void modular_release(ModularPlan& mp);
 hipError_t launch_count_equal(const int32_t* a, int n, int32_t v, int32_t* out,
                               hipStream_t s);
 
-// Launch-shape tuning shared by the solver handle and the autotuner.
-void set_tune(const bode_config& c, int block, int lanes_vdp, int lanes_lin,
-              int row_tile);
-int get_row_tile(const bode_config& c);
+// Launch shapes, per configuration shape, shared by the solver handle and
+// the autotuner (0 in a field: the library default).
+struct Tune {
+  int block = 0;      // analytic: threads per workgroup of the solve kernel
+  int lanes_vdp = 0;  // analytic: lanes launched for each kind of instance
+  int lanes_lin = 0;
+  int waves = 0;      // neural: wavefronts per 16-row tile (4 or 8)
+  int rounds = 0;     // neural per-stage path: rounds per graph / read-back
+};
+// set_tune also rewrites the tune cache file; set_tune_candidate only
+// changes the shape used by the next solves (the autotuner's trials).
+void set_tune(const bode_config& c, const Tune& t);
+void set_tune_candidate(const bode_config& c, const Tune& t);
+Tune get_tune(const bode_config& c);
 void set_thread_error(const std::string& m);
 int autotune(const bode_config* cfg, const bode_problem* p, void* workspace,
              size_t workspace_bytes, void* stream);

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -39,15 +40,108 @@ struct Layout {
   }
 };
 
-// Launch shapes chosen by solver_autotune, per (rhs, precision, method, B, D).
-struct Tune {
-  int block = 0, lanes_vdp = 0, lanes_lin = 0, row_tile = 0;
-};
+// Launch shapes chosen by solver_autotune, per device architecture and
+// configuration shape (right-hand side, precision, method, B, D, E, hidden
+// width, plain BF16).  When BATCHODE_TUNE_CACHE names a file, the shapes
+// are read from it on first use and every autotune rewrites it: one JSON
+// object per line.
+using bode::Tune;
+typedef std::tuple<std::string, int, int, int, int, int, int, int, int> TuneKey;
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, Tune> g_tune;
+std::map<TuneKey, Tune> g_tune;
+bool g_tune_loaded = false;
 
-std::tuple<int, int, int, int, int> tune_key(const bode_config& c) {
-  return std::make_tuple(c.rhs, c.precision, c.method, c.B, c.D);
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+TuneKey tune_key(const bode_config& c) {
+  return TuneKey(device_arch(), c.rhs, c.precision, c.method, c.B, c.D, c.E,
+                 c.rhs == BODE_RHS_ANALYTIC ? 0 : c.mlp_hidden,
+                 c.precision == BODE_BF16 ? c.plain_bf16 : 0);
+}
+
+// The integer after "name": in a line of the cache (absent: fallback).
+long json_int(const std::string& line, const char* name, long fallback) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t p = line.find(pat);
+  if (p == std::string::npos) return fallback;
+  return std::strtol(line.c_str() + p + pat.size(), nullptr, 10);
+}
+
+std::string json_str(const std::string& line, const char* name) {
+  const std::string pat = std::string("\"") + name + "\":\"";
+  const size_t p = line.find(pat);
+  if (p == std::string::npos) return "";
+  const size_t q = line.find('"', p + pat.size());
+  return q == std::string::npos ? "" : line.substr(p + pat.size(),
+                                                   q - p - pat.size());
+}
+
+const char* tune_cache_path() {
+  const char* p = std::getenv("BATCHODE_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+// Caller holds g_tune_mu.
+void load_tune_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char buf[1024];
+  while (std::fgets(buf, sizeof buf, f)) {
+    const std::string line(buf);
+    const std::string arch = json_str(line, "arch");
+    if (arch.empty()) continue;
+    TuneKey k(arch, (int)json_int(line, "rhs", -1),
+              (int)json_int(line, "precision", -1),
+              (int)json_int(line, "method", -1), (int)json_int(line, "B", -1),
+              (int)json_int(line, "D", -1), (int)json_int(line, "E", -1),
+              (int)json_int(line, "H", -1), (int)json_int(line, "plain", -1));
+    Tune t;
+    t.block = (int)json_int(line, "block", 0);
+    t.lanes_vdp = (int)json_int(line, "lanes_vdp", 0);
+    t.lanes_lin = (int)json_int(line, "lanes_lin", 0);
+    t.waves = (int)json_int(line, "waves", 0);
+    t.rounds = (int)json_int(line, "rounds", 0);
+    g_tune[k] = t;
+  }
+  std::fclose(f);
+}
+
+// Caller holds g_tune_mu.  Rewrites the whole cache (temporary file, then
+// rename), so a reader never sees a half-written line.
+bool save_tune_cache() {
+  const char* path = tune_cache_path();
+  if (!path) return true;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  for (const auto& kv : g_tune) {
+    const TuneKey& k = kv.first;
+    const Tune& t = kv.second;
+    std::fprintf(f,
+                 "{\"arch\":\"%s\",\"rhs\":%d,\"precision\":%d,\"method\":%d,"
+                 "\"B\":%d,\"D\":%d,\"E\":%d,\"H\":%d,\"plain\":%d,"
+                 "\"block\":%d,\"lanes_vdp\":%d,\"lanes_lin\":%d,"
+                 "\"waves\":%d,\"rounds\":%d}\n",
+                 std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k),
+                 std::get<6>(k), std::get<7>(k), std::get<8>(k), t.block,
+                 t.lanes_vdp, t.lanes_lin, t.waves, t.rounds);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
 }
 
 // One second stream per device for the linear-instance kernel, created on
@@ -262,11 +356,7 @@ void fill_analytic_args(bode_solver* s, bode::AnalyticArgs<R>* a) {
 // configuration's explicit tune fields.
 void apply_tune(bode_solver* s) {
   const bode_config& c = s->cfg;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(c));
-    if (it != g_tune.end()) s->tune = it->second;
-  }
+  s->tune = bode::get_tune(c);
   if (c.tune_block > 0) s->tune.block = c.tune_block;
   if (c.tune_lanes > 0) s->tune.lanes_vdp = s->tune.lanes_lin = c.tune_lanes;
 }
@@ -784,25 +874,50 @@ int solver_autotune(const bode_config* cfg, const bode_problem* p,
   return bode::autotune(cfg, p, workspace, workspace_bytes_, stream);
 }
 
+int solver_get_tune(const bode_config* cfg, int32_t* shape) {
+  try {
+    const std::string msg = check_config(cfg);
+    if (!msg.empty()) return fail(nullptr, BODE_EINVAL, msg);
+    if (!shape) return fail(nullptr, BODE_EINVAL, "shape is NULL");
+    const Tune t = bode::get_tune(*cfg);
+    shape[0] = t.block;
+    shape[1] = t.lanes_vdp;
+    shape[2] = t.lanes_lin;
+    shape[3] = t.waves;
+    shape[4] = t.rounds;
+    return BODE_OK;
+  } catch (...) {
+    return fail(nullptr, BODE_EHIP, "unknown error in solver_get_tune");
+  }
+}
+
 }  // extern "C"
 
 namespace bode {
 
-void set_tune(const bode_config& c, int block, int lanes_vdp, int lanes_lin,
-              int row_tile) {
+void set_tune(const bode_config& c, const Tune& t) {
+  const TuneKey k = tune_key(c);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  Tune t;
-  t.block = block;
-  t.lanes_vdp = lanes_vdp;
-  t.lanes_lin = lanes_lin;
-  t.row_tile = row_tile;
-  g_tune[tune_key(c)] = t;
+  load_tune_cache();
+  g_tune[k] = t;
+  if (!save_tune_cache())
+    std::fprintf(stderr, "batchode: cannot write the tune cache %s\n",
+                 tune_cache_path());
 }
 
-int get_row_tile(const bode_config& c) {
+void set_tune_candidate(const bode_config& c, const Tune& t) {
+  const TuneKey k = tune_key(c);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(tune_key(c));
-  return it == g_tune.end() ? 0 : it->second.row_tile;
+  load_tune_cache();
+  g_tune[k] = t;
+}
+
+Tune get_tune(const bode_config& c) {
+  const TuneKey k = tune_key(c);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_cache();
+  auto it = g_tune.find(k);
+  return it == g_tune.end() ? Tune() : it->second;
 }
 
 void set_thread_error(const std::string& m) { g_thread_error = m; }

@@ -285,20 +285,93 @@ def test_single_instance_and_user_h0():
     assert g["n_feval"][0] == 1 + 6 * g["n_attempted"][0]
 
 
-def test_autotune_keeps_results():
-    flush("autotune")
-    p = W.uneven_batch(B=4096)
-    dp = bd.device_problem(p, "fp32")
-    s = bd.Solver(dp, method="dopri5", precision="fp32")
+def autotune(p, precision, rhs=bd.RHS_ANALYTIC, **kw):
+    dp = bd.device_problem(p, precision)
+    s = bd.Solver(dp, method="dopri5", precision=precision, rhs=rhs, **kw)
     bd.solver_autotune(s.cfg, s.prob, s.workspace.data_ptr(),
                        s.workspace.numel(), s.stream.cuda_stream)
     torch.cuda.synchronize()
+    shape = bd.solver_get_tune(s.cfg)
     s.close()
-    g1, _ = run_gpu(p, method="dopri5", precision="fp32")
-    g2, _ = run_gpu(p, method="dopri5", precision="fp32", tune_block=64,
-                    tune_lanes=4096)
-    np.testing.assert_array_equal(g1["y_final"], g2["y_final"])
-    np.testing.assert_array_equal(g1["n_accepted"], g2["n_accepted"])
+    return shape
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_keeps_results(precision):
+    """The autotuner's shape (threads per workgroup, lanes) changes which
+    lane solves which instance, never an instance's arithmetic: a solve
+    with the tuned shape equals, bit for bit, solves with fixed shapes."""
+    flush(f"autotune analytic {precision}")
+    p = W.uneven_batch(B=4096)
+    shape = autotune(p, precision)
+    flush(f"  tuned {shape}")
+    assert shape["block"] in (64, 128, 256) and shape["lanes_vdp"] > 0
+    g1, _ = run_gpu(p, method="dopri5", precision=precision)
+    for blk, lanes in ((64, 4096), (256, 1024)):
+        g2, _ = run_gpu(p, method="dopri5", precision=precision,
+                        tune_block=blk, tune_lanes=lanes)
+        np.testing.assert_array_equal(g1["y_final"], g2["y_final"])
+        np.testing.assert_array_equal(g1["y_eval"], g2["y_eval"])
+        np.testing.assert_array_equal(g1["n_accepted"], g2["n_accepted"])
+        np.testing.assert_array_equal(g1["n_rejected"], g2["n_rejected"])
+
+
+@pytest.mark.parametrize("precision,keep", [("bf16", 0), ("fp32", 0),
+                                            ("bf16", 1), ("fp64", 0)])
+def test_autotune_neural_shapes_bitwise(precision, keep):
+    """Neural fields: every candidate of the autotuner (4 or 8 wavefronts per
+    16-row tile; 4, 8 or 16 rounds per graph on the per-stage path) gives
+    bitwise the solve of the default shape, and the tuned one is kept."""
+    from paper_2210_12375_amd import binding
+    flush(f"autotune neural {precision} keep={keep}")
+    p = W.neural_ode(B=512, hidden=256)
+    ref, _ = run_gpu(p, method="dopri5", precision=precision, rhs=bd.RHS_MLP,
+                     keep_dense=keep)
+    shape = autotune(p, precision, rhs=bd.RHS_MLP, keep_dense=keep)
+    flush(f"  tuned {shape}")
+    got, _ = run_gpu(p, method="dopri5", precision=precision, rhs=bd.RHS_MLP,
+                     keep_dense=keep)
+    np.testing.assert_array_equal(got["y_final"], ref["y_final"])
+    np.testing.assert_array_equal(got["n_attempted"], ref["n_attempted"])
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """BATCHODE_TUNE_CACHE: a process that autotunes writes the kept shape to
+    the file; a fresh process reads it back for the same configuration."""
+    import json
+    import os
+    import subprocess
+    import sys
+    flush("tune cache file")
+    cache = tmp_path / "tune.jsonl"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = f"""
+import sys, json
+sys.path.insert(0, {root!r}); sys.path.insert(0, {root + '/tests'!r})
+import torch
+from paper_2210_12375_amd import binding as bd
+from paper_2210_12375_amd import workloads as W
+p = W.uneven_batch(B=2048)
+dp = bd.device_problem(p, "fp32")
+s = bd.Solver(dp, method="dopri5", precision="fp32")
+if sys.argv[1] == "tune":
+    bd.solver_autotune(s.cfg, s.prob, s.workspace.data_ptr(),
+                       s.workspace.numel(), s.stream.cuda_stream)
+    torch.cuda.synchronize()
+print(json.dumps(bd.solver_get_tune(s.cfg)), flush=True)
+s.close()
+"""
+    env = dict(os.environ, BATCHODE_TUNE_CACHE=str(cache))
+    outs = []
+    for mode in ("tune", "read"):
+        r = subprocess.run([sys.executable, "-c", code, mode], env=env,
+                           capture_output=True, text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    assert outs[0] == outs[1] and outs[0]["block"] > 0, outs
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and json.loads(lines[0])["B"] == 2048
+    assert json.loads(lines[0])["arch"].startswith("gfx")
 
 
 @pytest.mark.parametrize("ctrl", ["H312PID", "PID"])
