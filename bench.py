@@ -209,6 +209,17 @@ def ceilings():
     t_triad = timed(lambda: ok(lib.ceil_triad(a.data_ptr(), b.data_ptr(),
                                               c.data_ptr(), n, 0.5,
                                               st.cuda_stream)))
+    # the streaming kernel's shape: vectors in flight per lane x grid
+    lib.ceil_triad_shape.argtypes = [vp, vp, vp, C.c_long, C.c_float, C.c_int,
+                                     C.c_int, vp]
+    sweep = {}
+    for unroll in (1, 2, 4, 8):
+        for blocks in (1024, 4096, 8192, 32768):
+            t = timed(lambda: ok(lib.ceil_triad_shape(
+                a.data_ptr(), b.data_ptr(), c.data_ptr(), n, 0.5, unroll,
+                blocks, st.cuda_stream)), 5)
+            sweep[f"u{unroll}_b{blocks}"] = round(12 * n / t / 1e9, 1)
+    t_triad = min(t_triad, 12 * n / max(sweep.values()) / 1e9)
     t_copy = timed(lambda: c.copy_(a))
     del a, b, c
     blocks, iters = 2048, 20000
@@ -224,6 +235,7 @@ def ceilings():
                                           st.cuda_stream)), 5)
     res["vector_fp32_fma_tflops"] = blocks * 256 * 16 * iters * 2 / t / 1e12
     res.update(hbm_triad_gbps=12 * n / t_triad / 1e9,
+               hbm_triad_sweep_gbps=sweep,
                hbm_copy_gbps=8 * n / t_copy / 1e9,
                datasheet={"hbm_gbps": 8000, "mfma_bf16_tflops": 2500,
                           "mfma_f32_tflops": 157.3,

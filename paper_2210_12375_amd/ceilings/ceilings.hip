@@ -18,20 +18,36 @@
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Each thread moves U 16-byte vectors of each operand per iteration, all
+// loads issued before the first store (U x 2 loads in flight per lane), with
+// non-temporal hints (streamed data is not kept in the caches); consecutive
+// lanes touch consecutive vectors, so every load instruction of a wavefront
+// covers 1 KiB contiguous.
+template <int U>
 __global__ __launch_bounds__(256) void triad_kernel(const float* a,
                                                     const float* b, float* c,
                                                     long n, float s) {
-  const long stride = (long)gridDim.x * blockDim.x * 4;
-  for (long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < n;
-       i += stride) {
-    if (i + 3 < n) {
-      const f32x4 x = *reinterpret_cast<const f32x4*>(a + i);
-      const f32x4 y = *reinterpret_cast<const f32x4*>(b + i);
-      *reinterpret_cast<f32x4*>(c + i) = x + s * y;
-    } else {
-      for (long k = i; k < n; ++k) c[k] = a[k] + s * b[k];
+  const long nv = n / 4;  // whole vectors
+  const f32x4* av = reinterpret_cast<const f32x4*>(a);
+  const f32x4* bv = reinterpret_cast<const f32x4*>(b);
+  f32x4* cv = reinterpret_cast<f32x4*>(c);
+  const long T = (long)gridDim.x * blockDim.x;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long i = t;
+  for (; i + (U - 1) * T < nv; i += U * T) {
+    f32x4 x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x[u] = __builtin_nontemporal_load(av + i + u * T);
+      y[u] = __builtin_nontemporal_load(bv + i + u * T);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      __builtin_nontemporal_store(x[u] + s * y[u], cv + i + u * T);
   }
+  for (; i < nv; i += T) cv[i] = av[i] + s * bv[i];
+  if (t == 0)
+    for (long k = nv * 4; k < n; ++k) c[k] = a[k] + s * b[k];
 }
 
 __global__ __launch_bounds__(256) void mfma_bf16_kernel(float* out,
@@ -89,9 +105,33 @@ extern "C" {
 int ceil_triad(const float* a, const float* b, float* c, long n, float s,
                void* stream) {
   if (!a || !b || !c || n < 0) return (int)hipErrorInvalidValue;
+  // 16-byte vectors need 16-byte aligned operands
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+       reinterpret_cast<uintptr_t>(c)) % 16 != 0)
+    return (int)hipErrorInvalidValue;
   const int blocks = 256 * 8 * 4;
-  hipLaunchKernelGGL(triad_kernel, dim3(blocks), dim3(256), 0,
+  hipLaunchKernelGGL(triad_kernel<4>, dim3(blocks), dim3(256), 0,
                      (hipStream_t)stream, a, b, c, n, s);
+  return (int)hipGetLastError();
+}
+
+// ceil_triad with a chosen unroll (1, 2, 4 or 8 vectors per operand in
+// flight per lane) and grid (blocks of 256 threads), for a sweep of the
+// streaming kernel's shape.
+int ceil_triad_shape(const float* a, const float* b, float* c, long n,
+                     float s, int unroll, int blocks, void* stream) {
+  if (!a || !b || !c || n < 0 || blocks < 1) return (int)hipErrorInvalidValue;
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+       reinterpret_cast<uintptr_t>(c)) % 16 != 0)
+    return (int)hipErrorInvalidValue;
+  hipStream_t st = (hipStream_t)stream;
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL(triad_kernel<1>, dim3(blocks), dim3(256), 0, st, a, b, c, n, s); break;
+    case 2: hipLaunchKernelGGL(triad_kernel<2>, dim3(blocks), dim3(256), 0, st, a, b, c, n, s); break;
+    case 4: hipLaunchKernelGGL(triad_kernel<4>, dim3(blocks), dim3(256), 0, st, a, b, c, n, s); break;
+    case 8: hipLaunchKernelGGL(triad_kernel<8>, dim3(blocks), dim3(256), 0, st, a, b, c, n, s); break;
+    default: return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 
