@@ -45,7 +45,7 @@ def parse():
                     help="skip the neural-field workloads")
     ap.add_argument("--study", default="",
                     choices=["", "cadjoint", "neural", "ceilings", "hbm",
-                             "paper", "fwdbwd"],
+                             "paper", "fwdbwd", "fig1"],
                     help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
@@ -590,6 +590,50 @@ def joint_study(bd, W):
             "drawn phases of one cycle, atol = rtol = 1e-6, FP64 dopri5"}
 
 
+def fig1_traces(bd, W, mu=25.0, B=16, grid=48):
+    """Section 4.1, Figure 1: the step sizes of the joint (coupled) solve of
+    B Van der Pol oscillators at different phases of one cycle, mu = 25,
+    beside the step sizes each oscillator takes when solved independently
+    (FP64 Dormand-Prince, atol = rtol = 1e-6): on a grid of times over the
+    cycle, the joint step in force and the smallest, median and largest
+    independent step in force."""
+    import torch
+    p = W.vdp_phases(B=B, mu=mu)
+    dp = bd.device_problem(p, "fp64")
+    rec = {}
+    for joint in (0, 1):
+        s = bd.Solver(dp, method="dopri5", precision="fp64", joint=joint,
+                      record_cap=8192).solve()
+        h, n = s.steps()
+        rec[joint] = (h.cpu().numpy(), n.cpu().numpy())
+        s.close()
+    torch.cuda.synchronize()
+
+    def accepted(h, n, i):
+        a = h[i, :n[i]]
+        a = a[a > 0]
+        return np.concatenate([[p["t0"][i]], p["t0"][i] + np.cumsum(a)]), a
+
+    tj, hj = accepted(*rec[1], 0)
+    ind = [accepted(*rec[0], i) for i in range(B)]
+    times = np.linspace(p["t0"][0], p["t_end"][0], grid, endpoint=False)
+    rows = []
+    for t in times:
+        in_force = lambda tt, hh: float(hh[min(np.searchsorted(tt, t, "right")
+                                             - 1, len(hh) - 1)])
+        hi = [in_force(tt, hh) for tt, hh in ind]
+        rows.append([round(float(t), 4), in_force(tj, hj), float(np.min(hi)),
+                     float(np.median(hi)), float(np.max(hi))])
+    return {"workload": f"{B} Van der Pol oscillators, mu = {mu}, uniformly "
+                        "drawn phases of one cycle, atol = rtol = 1e-6, FP64 "
+                        "dopri5",
+            "joint_accepted_steps": int(len(hj)),
+            "independent_accepted_steps": [int(len(hh)) for _, hh in ind],
+            "columns": ["t", "h_joint", "h_independent_min",
+                        "h_independent_median", "h_independent_max"],
+            "rows": rows}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -620,6 +664,9 @@ def main():
         return
     if a.study == "hbm":
         print(json.dumps({"hbm_study": hbm_study(bd, W)}), flush=True)
+        return
+    if a.study == "fig1":
+        print(json.dumps({"fig1_traces": fig1_traces(bd, W)}), flush=True)
         return
     if a.study == "fwdbwd":
         print(json.dumps({"neural": neural_suite(bd, W, rl, a.steps, a.warmup,

@@ -121,8 +121,9 @@ typedef struct {
                          the others are BODE_INVALID) are solved as one
                          system with one step size, one error norm (RMS over
                          all their components) and one accept/reject
-                         decision.  ANALYTIC fields, record_cap = 0 and
-                         keep_dense = 0 only.  0: independent instances.   */
+                         decision.  ANALYTIC fields and keep_dense = 0
+                         only; with record_cap every member's row holds the
+                         joint attempts.  0: independent instances.        */
   int32_t eager;      /* neural fields: 1 launches every kernel of the round
                          loops directly; 0 (default) captures a block of
                          rounds (and of continuous-adjoint attempts) into a

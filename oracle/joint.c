@@ -185,6 +185,10 @@ int orc_solve_joint(const orc_problem* P, const orc_options* O,
       } else {
         fac = fmax(O->fac_min, O->safety * pow(err, -1.0 / 5.0));
       }
+      if (O->h_rec && natt <= O->rec_cap) /* the joint attempt, per member */
+        for (int32_t i = 0; i < B; ++i)
+          if (off[i] >= 0)
+            O->h_rec[(long)i * O->rec_cap + natt - 1] = accept ? hs : -hs;
       if (accept) {
         const double tnew = last ? te : t + hs;
         while (cursor < E && teval[cursor] <= tnew) {

@@ -215,13 +215,20 @@ def solve(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
 
 def solve_joint(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
                 beta2=PI_CONTROLLER["beta2"], beta3=0.0, safety=0.9,
-                fac_min=0.2, fac_max=10.0, max_steps=100000, variant=None):
+                fac_min=0.2, fac_max=10.0, max_steps=100000, variant=None,
+                record_cap=0):
     """Joint (coupled) solve of section 4.1: the batch as one stacked system
-    with one step size and one error norm; returns the arrays of solve()."""
+    with one step size and one error norm; returns the arrays of solve()
+    (with record_cap, h_rec holds the joint attempts in every member's
+    row)."""
     lib = _load(variant)
     m = _Marshalled(problem)
     o = _options(method, beta1, beta2, safety, fac_min, fac_max, max_steps, 0)
     o.beta3 = beta3
+    h_rec = None
+    if record_cap > 0:
+        h_rec = np.full((m.B, record_cap), np.nan)
+        o.h_rec, o.rec_cap = _ptr(h_rec), record_cap
     y_eval = np.zeros((m.B, m.E, m.D))
     y_final = np.zeros((m.B, m.D))
     stats = np.zeros((5, m.B), dtype=np.int32)
@@ -229,9 +236,12 @@ def solve_joint(problem, method="dopri5", beta1=PI_CONTROLLER["beta1"],
                              _ptr(y_final), _ptr(stats, _ip))
     if rc != 0:
         raise ValueError("oracle rejected the problem description")
-    return dict(y_eval=y_eval, y_final=y_final, n_attempted=stats[0],
-                n_accepted=stats[1], n_rejected=stats[2], n_feval=stats[3],
-                status=stats[4])
+    out = dict(y_eval=y_eval, y_final=y_final, n_attempted=stats[0],
+               n_accepted=stats[1], n_rejected=stats[2], n_feval=stats[3],
+               status=stats[4])
+    if h_rec is not None:
+        out["h_rec"] = h_rec
+    return out
 
 
 def accepted_steps(h_rec, n_attempted):

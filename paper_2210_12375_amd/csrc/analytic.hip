@@ -857,7 +857,7 @@ __global__ __launch_bounds__(kJointThreads) void joint_solve_kernel(
   __shared__ double red[kJointThreads / 64];
   __shared__ JointState js;
   __shared__ int32_t acc_s, cur_new;
-  __shared__ double tnew_s, fac_s;
+  __shared__ double tnew_s, fac_s, err_s;
   const int tid = threadIdx.x;
   const long B = a.B, D = a.D;
   if (tid == 0) js = *a.js;
@@ -919,8 +919,16 @@ __global__ __launch_bounds__(kJointThreads) void joint_solve_kernel(
       }
       cur_new = cur;
       fac_s = fac;
+      err_s = err;
     }
     __syncthreads();
+    if (a.h_rec != nullptr && js.n_att <= a.rec_cap)  // every member's row
+      for (int i = tid; i < B; i += kJointThreads) {
+        if (a.st.status[i] == kInvalid) continue;
+        const long o = (long)i * a.rec_cap + js.n_att - 1;
+        a.h_rec[o] = acc_s ? double(hs) : -double(hs);
+        a.e_rec[o] = err_s;
+      }
     if (acc_s) {  // dense outputs in (t, t_new], then y <- Y7, k1 <- k7
       for (int i = tid; i < B; i += kJointThreads) {
         if (a.st.status[i] == kInvalid) continue;

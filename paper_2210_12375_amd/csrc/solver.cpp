@@ -221,10 +221,8 @@ std::string check_config(const bode_config* c) {
     return "controller needs safety > 0, 0 < fac_min <= 1 <= fac_max, "
            "finite beta1 >= 0, finite beta2 and beta3";
   if (c->joint != 0 && c->joint != 1) return "joint must be 0 or 1";
-  if (c->joint && (c->rhs != BODE_RHS_ANALYTIC || c->record_cap != 0 ||
-                   c->keep_dense != 0))
-    return "joint mode is built for analytic fields without record_cap or "
-           "keep_dense";
+  if (c->joint && (c->rhs != BODE_RHS_ANALYTIC || c->keep_dense != 0))
+    return "joint mode is built for analytic fields without keep_dense";
   if (c->fixed_step != 0 && c->fixed_step != 1)
     return "fixed_step must be 0 or 1";
   if (c->eager != 0 && c->eager != 1) return "eager must be 0 or 1";

@@ -63,9 +63,9 @@ int main() {
       {"beta3 inf", [](bode_config& x) { x.beta3 = 1.0 / 0.0; }},
       {"record_cap", [](bode_config& x) { x.record_cap = -2; }},
       {"ckpt without record", [](bode_config& x) { x.ckpt_every = 2; }},
-      {"joint + record", [](bode_config& x) {
+      {"joint + keep_dense", [](bode_config& x) {
          x.joint = 1;
-         x.record_cap = 8;
+         x.keep_dense = 1;
        }},
       {"fixed + joint", [](bode_config& x) {
          x.fixed_step = 1;

@@ -91,3 +91,34 @@ def test_joint_step_slices_match_one_solve():
     np.testing.assert_array_equal(s.y_eval.cpu().numpy(), g["y_eval"])
     np.testing.assert_array_equal(s.stats()["n_attempted"].cpu().numpy(),
                                   g["n_attempted"])
+
+
+@pytest.mark.parametrize("method", ["dopri5", "tsit5"])
+def test_joint_record(method):
+    """The joint attempt record (every member's row, section 4.1's shared
+    step): the same in every member, each decision and proposal following
+    from the recorded joint norm by the controller law, and step for step
+    the oracle's joint record (well-conditioned batch: mu = 5, 16
+    members)."""
+    from gpu_helpers import controller_record_check
+    flush(f"joint record {method}")
+    p = W.vdp_phases(B=16, mu=5.0, E=4)
+    g, _ = run_gpu(p, method=method, joint=1, record_cap=4096)
+    r = oracle.solve_joint(p, method=method, record_cap=4096)
+    n = int(g["n_rec"][0])
+    assert np.all(g["n_rec"] == n) and n == int(r["n_attempted"][0])
+    for i in range(1, 16):
+        np.testing.assert_array_equal(g["h_rec"][i, :n], g["h_rec"][0, :n])
+    q = W.subset(p, np.array([0]))
+    controller_record_check(q, g["h_rec"][:1, :n], g["e_rec"][:1, :n],
+                            g["n_rec"][:1], None, "fp64")
+    np.testing.assert_array_equal(np.sign(g["h_rec"][0, :n]),
+                                  np.sign(r["h_rec"][0, :n]))
+    # the embedded estimate cancels terms ~1e6 times its size, so rounding
+    # differences of the stages (contracted multiply-adds on the GPU) move
+    # the norm, and every later step size, by ~1e-10 relative; the clip of
+    # the last step to t_end inherits the time's drift (~1e-10 absolute)
+    span = float(p["t_end"][0] - p["t0"][0])
+    np.testing.assert_allclose(np.abs(g["h_rec"][0, :n]),
+                               np.abs(r["h_rec"][0, :n]), rtol=1e-8,
+                               atol=1e-10 * span)

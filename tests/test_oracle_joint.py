@@ -86,3 +86,22 @@ def test_stacked_oscillators_need_more_steps():
     assert np.all(ind["status"] == 1) and np.all(j["status"] == 1)
     ratio = j["n_attempted"][0] / ind["n_attempted"].mean()
     assert ratio > 2.0, ratio
+
+
+def test_joint_record_of_one_member_is_the_independent_record():
+    """The joint attempt record (every member's row) of a batch of one is the
+    independent solve's record, and every member of a larger joint batch
+    carries the same record, whose length is the joint attempt count."""
+    p = W.vdp_batch(B=5)
+    q = W.subset(p, np.array([2]))
+    a = oracle.solve(q, method="dopri5", record_cap=512)
+    b = oracle.solve_joint(q, method="dopri5", record_cap=512)
+    n = int(a["n_attempted"][0])
+    np.testing.assert_array_equal(a["h_rec"][0, :n], b["h_rec"][0, :n])
+    r = oracle.solve_joint(W.vdp_phases(B=6, mu=5.0), method="dopri5",
+                           record_cap=4096)
+    n = int(r["n_attempted"][0])
+    assert np.all(r["n_attempted"] == n)
+    for i in range(1, 6):
+        np.testing.assert_array_equal(r["h_rec"][i, :n], r["h_rec"][0, :n])
+    assert np.sum(r["h_rec"][0, :n] > 0) == r["n_accepted"][0]
