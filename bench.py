@@ -45,7 +45,7 @@ def parse():
                     help="skip the neural-field workloads")
     ap.add_argument("--study", default="",
                     choices=["", "cadjoint", "neural", "ceilings", "hbm",
-                             "paper", "fwdbwd", "fig1"],
+                             "paper", "fwdbwd", "fig1", "sweep"],
                     help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
@@ -590,6 +590,47 @@ def joint_study(bd, W):
             "drawn phases of one cycle, atol = rtol = 1e-6, FP64 dopri5"}
 
 
+def batch_sweep(bd, W, rl, steps=3, warmup=1):
+    """Matrix-core utilisation against batch size: the fused forward solve of
+    the 65-256-256-64 MLP field (BF16, split activations) from 4,096 to
+    65,536 instances and of the CNF field (17-512-512-16 with tangent rows)
+    from 8,192 to 65,536, each timed whole (median of `steps`) with its
+    model flops (6 evaluations per attempt round over every row)."""
+    import torch
+    out = {}
+    for name, make, rhs, sizes in (
+            ("mlp_bf16", W.neural_ode, bd.RHS_MLP, (4096, 16384, 65536)),
+            ("cnf_bf16", W.cnf_density, bd.RHS_CNF, (8192, 32768, 65536))):
+        rows = []
+        for B in sizes:
+            p = make(B=B)
+            dp = bd.device_problem(p, "bf16")
+            times, st = [], None
+            for k in range(warmup + steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = bd.Solver(dp, method="dopri5", precision="bf16",
+                              rhs=rhs).solve()
+                torch.cuda.synchronize()
+                if k >= warmup:
+                    times.append(time.perf_counter() - t0)
+                st = s.stats()
+                s.close()
+            ms = float(np.median(times)) * 1e3
+            att = st["n_attempted"].cpu().numpy()
+            d = p["y0"].shape[1] - (1 if rhs == bd.RHS_CNF else 0)
+            H = p["mlp"]["W1"].shape[1]
+            row = rl.mlp_flops_per_row(d, H) * (2 if rhs == bd.RHS_CNF else 1)
+            fl = float((2 + 6 * att).sum()) * row
+            rows.append(dict(B=B, ms=round(ms, 3), attempts_max=int(att.max()),
+                             model_tflops=round(fl / (ms * 1e-3) / 1e12, 1)))
+            print(f"# sweep {name} B={B}: {ms:.2f} ms, "
+                  f"{rows[-1]['model_tflops']} model TFLOP/s", file=sys.stderr,
+                  flush=True)
+        out[name] = rows
+    return out
+
+
 def fig1_traces(bd, W, mu=25.0, B=16, grid=48):
     """Section 4.1, Figure 1: the step sizes of the joint (coupled) solve of
     B Van der Pol oscillators at different phases of one cycle, mu = 25,
@@ -664,6 +705,9 @@ def main():
         return
     if a.study == "hbm":
         print(json.dumps({"hbm_study": hbm_study(bd, W)}), flush=True)
+        return
+    if a.study == "sweep":
+        print(json.dumps({"batch_sweep": batch_sweep(bd, W, rl)}), flush=True)
         return
     if a.study == "fig1":
         print(json.dumps({"fig1_traces": fig1_traces(bd, W)}), flush=True)

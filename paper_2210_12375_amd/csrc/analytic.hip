@@ -85,14 +85,18 @@ __host__ __device__ constexpr bool dense_uses(int j) {
 template <typename R>
 constexpr bool kCompensated = std::is_same<R, float>::value;
 
-template <typename R, int N>
+// TW: evaluation times held in registers.  tw[0] is the instance's next
+// evaluation time; each emission shifts the window and requests the time TW
+// places ahead, so up to TW - 1 of those loads are in flight.  Two (the
+// default) covers an emission per step; solves with many evaluation times
+// per step (the paper's loop-time workload: about four) take eight.
+template <typename R, int N, int TW = 2>
 struct Lane {
   R y[N];
   R yc[N];  // compensation of y (FP32), zero in FP64
   R k[7][N];
-  // next_te is the instance's next evaluation time, next_te2 the one after:
-  // it is fetched one emission early, so an emission never waits on memory.
-  double t, te, next_te, next_te2;
+  double t, te;
+  double tw[TW];
   R h, err_prev, err_prev2, rtol, atol;
   int32_t n_att, n_acc, n_rej, n_fe, status, cursor, prev_rej, dim, inst;
 };
@@ -121,8 +125,9 @@ __device__ __forceinline__ void fill_nan_row(R* row, int D, int dim) {
   for (int q = 0; q < D; ++q) row[q] = q < dim ? quiet_nan<R>() : R(0);
 }
 
-template <typename R, int N>
-__device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<R, N>& L) {
+template <typename R, int N, int TW>
+__device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i,
+                                          Lane<R, N, TW>& L) {
   const State<R>& s = a.st;
   L.inst = i;
   L.dim = a.dim[i];
@@ -140,9 +145,10 @@ __device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<
   L.status = s.status[i];
   L.cursor = s.cursor[i];
   L.prev_rej = s.prev_rej[i];
-  L.next_te = L.cursor < a.E ? a.t_eval[(long)i * a.E + L.cursor] : INFINITY;
-  L.next_te2 =
-      L.cursor + 1 < a.E ? a.t_eval[(long)i * a.E + L.cursor + 1] : INFINITY;
+#pragma unroll
+  for (int w = 0; w < TW; ++w)
+    L.tw[w] = L.cursor + w < a.E ? a.t_eval[(long)i * a.E + L.cursor + w]
+                                 : INFINITY;
   const R* yr = s.y + (long)i * a.D;
   const R* kr = s.k1 + (long)i * a.D;
   const R* cr = s.yc + (long)i * a.D;
@@ -154,8 +160,9 @@ __device__ __forceinline__ void load_lane(const AnalyticArgs<R>& a, int i, Lane<
   }
 }
 
-template <typename R, int N>
-__device__ __forceinline__ void store_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
+template <typename R, int N, int TW>
+__device__ __forceinline__ void store_lane(const AnalyticArgs<R>& a,
+                                           const Lane<R, N, TW>& L) {
   const State<R>& s = a.st;
   const int i = L.inst;
   s.t[i] = L.t;
@@ -175,8 +182,9 @@ __device__ __forceinline__ void store_lane(const AnalyticArgs<R>& a, const Lane<
 }
 
 // Writes the final state, and NaN for evaluation times never reached.
-template <typename R, int N>
-__device__ __forceinline__ void finish_lane(const AnalyticArgs<R>& a, const Lane<R, N>& L) {
+template <typename R, int N, int TW>
+__device__ __forceinline__ void finish_lane(const AnalyticArgs<R>& a,
+                                            const Lane<R, N, TW>& L) {
   store_lane(a, L);
   write_row<R, N>(a.y_final + (long)L.inst * a.D, a.D, L.y, L.dim);
   if (L.status != kSuccess)
@@ -190,9 +198,9 @@ __device__ __forceinline__ void finish_lane(const AnalyticArgs<R>& a, const Lane
 // REC: write the attempt record; KEEP: keep the interpolant for solver_eval.
 // The controller is branch-free (selects); only the rare paths (dense output,
 // the step limit) branch.
-template <typename R, class M, class F, bool REC, bool KEEP>
-__device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>& L,
-                        const F& f) {
+template <typename R, class M, class F, bool REC, bool KEEP, int TW>
+__device__ __forceinline__ void attempt(const AnalyticArgs<R>& a,
+                                        Lane<R, F::N, TW>& L, const F& f) {
   constexpr int N = F::N;
   if (__builtin_expect(L.n_att >= a.ctrl.max_steps, 0)) {
     L.status = kMaxSteps;
@@ -288,10 +296,10 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
     const double tnew = last ? L.te : L.t + double(hs);
     // Dense output at this instance's own evaluation times in (t, t_new]
     // (Horner in theta, then the stage combination).
-    while (__builtin_expect(L.next_te <= tnew, 0)) {
+    while (__builtin_expect(L.tw[0] <= tnew, 0)) {
       // theta = (t_e - t_n) / h: the difference in double, the quotient in
       // the state's precision
-      const R th = ctl_div(R(L.next_te - L.t), hs);
+      const R th = ctl_div(R(L.tw[0] - L.t), hs);
       R w[7];
 #pragma unroll
       for (int j = 0; j < 7; ++j)
@@ -310,10 +318,11 @@ __device__ __forceinline__ void attempt(const AnalyticArgs<R>& a, Lane<R, F::N>&
       write_row_n<R, N>(a.y_eval + ((long)L.inst * a.E + L.cursor) * a.D,
                         a.D, out, L.dim);
       L.cursor += 1;
-      L.next_te = L.next_te2;
-      L.next_te2 = L.cursor + 1 < a.E
-                       ? a.t_eval[(long)L.inst * a.E + L.cursor + 1]
-                       : INFINITY;
+#pragma unroll
+      for (int w = 0; w + 1 < TW; ++w) L.tw[w] = L.tw[w + 1];
+      L.tw[TW - 1] = L.cursor + TW - 1 < a.E
+                         ? a.t_eval[(long)L.inst * a.E + L.cursor + TW - 1]
+                         : INFINITY;
     }
     if (KEEP) {
       const int i = L.inst;
@@ -368,10 +377,10 @@ __device__ __forceinline__ int fetch(const AnalyticArgs<R>& a, int kind) {
 
 constexpr int kLongRun = 256;
 
-template <typename R, class M, class F, bool REC, bool KEEP>
+template <typename R, class M, class F, bool REC, bool KEEP, int TW = 2>
 __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
                                                     int kind) {
-  Lane<R, F::N> L;
+  Lane<R, F::N, TW> L;
   F f;
   int inst = fetch(a, kind);
   while (inst >= 0) {
@@ -384,7 +393,7 @@ __global__ __launch_bounds__(256) void solve_kernel(AnalyticArgs<R> a,
       __builtin_amdgcn_s_waitcnt(0x0F70);
       int used = 0;
       while (L.status == kRunning && used < a.budget) {
-        attempt<R, M, F, REC, KEEP>(a, L, f);
+        attempt<R, M, F, REC, KEEP, TW>(a, L, f);
         ++used;
         // An instance still stepping after many attempts is on the batch's
         // critical path (the solve ends with its last step): its wavefront
@@ -984,11 +993,18 @@ hipError_t launch_analytic_init(const AnalyticArgs<R>& a, int, hipStream_t s) {
   return hipGetLastError();
 }
 
+constexpr int kWindowMinE = 64;
+
 template <typename R, class M, class F>
 void launch_solve_flags(const AnalyticArgs<R>& a, int kind, dim3 g, dim3 b,
                         hipStream_t s) {
   const bool rec = a.h_rec != nullptr, keep = a.keep_dense != 0;
-  if (rec && keep)
+  // many evaluation times per instance: the eight-time window (measured on
+  // the paper's 256-instance, 200-time Van der Pol workload)
+  if (!rec && !keep && a.E >= kWindowMinE)
+    hipLaunchKernelGGL((solve_kernel<R, M, F, false, false, 8>), g, b, 0, s,
+                       a, kind);
+  else if (rec && keep)
     hipLaunchKernelGGL((solve_kernel<R, M, F, true, true>), g, b, 0, s, a, kind);
   else if (rec)
     hipLaunchKernelGGL((solve_kernel<R, M, F, true, false>), g, b, 0, s, a,
