@@ -132,6 +132,129 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
   auto on = [&](int row) { return row < B && a.act[row] == kRunning; };
 
+  const float* b1 = a.w.fvec;
+  const float* w1t = b1 + H;
+  const float* b2 = b1 + 2 * H;
+  const int rq = (lane >> 4) * 4, col = lane & 15;
+  // tape column of accumulator row `row` of the 16-row tile (-1: none)
+  auto tk = [&](int row) -> long {
+    const bool primal = !CNF || row < PR;
+    const int g = r0 + (primal ? row : row - PR);
+    if (g >= B) return -1;
+    return kb + g + (primal ? 0 : B);
+  };
+  float keep[2][NTW][4];
+  if (a.act_in != nullptr) {
+    // The forward layers as the stage's field evaluation stored them: no
+    // layer is recomputed, so nothing here waits on anything but memory,
+    // and every load of the kernel's front half is issued at once (stage
+    // input, cotangent, probe, stored layers, time) before the first store.
+    constexpr int NE = (PR * 256 + 64 * WV - 1) / (64 * WV);
+    float Yr[NE], Kz[NE], Er[NE], Kl[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * (int)blockDim.x;
+      Yr[e] = Kz[e] = Er[e] = Kl[e] = 0.f;
+      if (idx < PR * din) {
+        const int r = idx / din, c = idx % din, row = r0 + r;
+        if (on(row)) {
+          Yr[e] = a.Y[(long)row * D + c];
+          Kz[e] = a.kap_s[(long)row * D + c];
+          if (CNF) {
+            Er[e] = a.eps[(long)row * D + c];
+            Kl[e] = a.kap_s[(long)row * D + din];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = rq + i;
+          const bool primal = !CNF || row < PR;
+          const int g = r0 + (primal ? row : row - PR);
+          // rows without this step read as zero (their stored values come
+          // from stale states)
+          keep[layer][t][i] =
+              g < B && a.act[g] == kRunning
+                  ? a.act_in[((long)(g + (primal ? 0 : B)) * 2 + layer) * H +
+                             n]
+                  : 0.f;
+        }
+      }
+    float tv = 0.f;
+    if (tid < PR && on(r0 + tid))
+      tv = float(a.bt[r0 + tid] + a.c * double(a.bh[r0 + tid]));
+    // layer-1 inputs and the cotangent gbar (kappa_z on primal rows,
+    // -kappa_l eps on tangent rows) into the tape; gbar into LDS
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * (int)blockDim.x;
+      if (idx < PR * din) {
+        const int r = idx / din, c = idx % din, row = r0 + r;
+        Op::put(Xh, PX, r * SX + c, Kz[e]);
+        if (row < B) {
+          a.T1in[(kb + row) * l1 + c] = Yr[e];
+          a.T3g[(kb + row) * din + c] = Kz[e];
+        }
+        if (CNF) {
+          const float gg = -Kl[e] * Er[e];
+          Op::put(Xh, PX, (PR + r) * SX + c, gg);
+          if (row < B) {
+            a.T1in[(kb + B + row) * l1 + c] = Er[e];
+            a.T3g[(kb + B + row) * din + c] = gg;
+          }
+        }
+      }
+    }
+    if (tid < PR && r0 + tid < B) {
+      const int row = r0 + tid;
+      a.T1in[(kb + row) * l1 + din] = tv;
+      a.T1in[(kb + row) * l1 + din + 1] = 1.f;
+      if (CNF) {
+        a.T1in[(kb + B + row) * l1 + din] = 0.f;
+        a.T1in[(kb + B + row) * l1 + din + 1] = 0.f;
+      }
+    }
+    // layer-2 and layer-3 inputs (the activations; on tangent rows the
+    // tangent activation from the partner row's tanh') and bias features
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+      float* Tin = layer == 0 ? a.T2in : a.T3in;
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = rq + i;
+          const bool primal = !CNF || row < PR;
+          float act = keep[layer][t][i];
+          if (CNF) {
+            const float ap = __shfl_xor(act, 32, 64);
+            if (!primal) act = (1.f - ap * ap) * act;
+          }
+          const long k = tk(row);
+          if (k >= 0) Tin[k * (H + 1) + n] = act;
+        }
+      }
+    }
+    for (int r = tid; r < RT; r += blockDim.x) {
+      const long k = tk(r);
+      if (k < 0) continue;
+      const float one = (!CNF || r < PR) ? 1.f : 0.f;
+      a.T2in[k * (H + 1) + H] = one;
+      a.T3in[k * (H + 1) + H] = one;
+    }
+    for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
+      const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
+      Op::put(Xh, PX, r * SX + c, 0.f);
+    }
+    __syncthreads();
+  } else {
   // prologue: Y_s and the probe into LDS, the layer-1 inputs into the tape
   for (int idx = tid; idx < PR * din; idx += blockDim.x) {
     const int r = idx / din, c = idx % din, row = r0 + r;
@@ -165,54 +288,9 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   }
   __syncthreads();
 
-  const float* b1 = a.w.fvec;
-  const float* w1t = b1 + H;
-  const float* b2 = b1 + 2 * H;
-  const int rq = (lane >> 4) * 4, col = lane & 15;
-  // tape column of accumulator row `row` of the 16-row tile (-1: none)
-  auto tk = [&](int row) -> long {
-    const bool primal = !CNF || row < PR;
-    const int g = r0 + (primal ? row : row - PR);
-    if (g >= B) return -1;
-    return kb + g + (primal ? 0 : B);
-  };
 
-  float keep[2][NTW][4];
-  if (a.act_in != nullptr) {
-    // the forward layers as the stage's field evaluation stored them
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-      float* Tin = layer == 0 ? a.T2in : a.T3in;
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        const int n = (wave * NTW + t) * 16 + col;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = rq + i;
-          const bool primal = !CNF || row < PR;
-          const int g = r0 + (primal ? row : row - PR);
-          // rows without this step read as zero (their stored values
-          // come from stale states)
-          const float kv =
-              g < B && a.act[g] == kRunning
-                  ? a.act_in[((long)(g + (primal ? 0 : B)) * 2 + layer) * H +
-                             n]
-                  : 0.f;
-          keep[layer][t][i] = kv;
-          float act = kv;
-          if (CNF) {
-            const float ap = __shfl_xor(kv, 32, 64);
-            if (!primal) act = (1.f - ap * ap) * kv;
-          }
-          const long k = tk(row);
-          if (k >= 0) Tin[k * (H + 1) + n] = act;
-        }
-      }
-    }
-  }
 #pragma unroll
   for (int layer = 0; layer < 2; ++layer) {
-    if (a.act_in != nullptr) break;
     f32x4 acc[1][NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -276,6 +354,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   }
   __syncthreads();
 
+  }
   // S2 = gbar W3^T, then S1 = G2 W2^T; epilogues form G2, G1
 #pragma unroll
   for (int layer = 1; layer >= 0; --layer) {
