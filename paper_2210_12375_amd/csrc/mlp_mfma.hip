@@ -107,29 +107,36 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
     any_running = 1;
   __syncthreads();
   const long kb = a.kb;
+  const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
   if (!any_running) {
-    // no row of the tile has this step: its cotangent rows of the tape are
-    // zero (the gradient GEMMs read every row; a tape holds several steps,
-    // so these rows may hold an earlier step's values)
-    for (int idx = tid; idx < PR * H; idx += blockDim.x) {
-      const int r = idx / H, c = idx % H, row = r0 + r;
+    // no row of the tile has this step: its rows of the tape are zero (the
+    // gradient GEMMs read every row; a tape holds several steps, so these
+    // rows may hold an earlier step's values, or nothing yet)
+    const int nr = CNF ? 2 : 1;
+    for (int idx = tid; idx < PR * (H + 1); idx += blockDim.x) {
+      const int r = idx / (H + 1), c = idx % (H + 1), row = r0 + r;
       if (row >= B) continue;
-      a.T1g[(kb + row) * H + c] = 0.f;
-      a.T2g[(kb + row) * H + c] = 0.f;
-      if (CNF) {
-        a.T1g[(kb + B + row) * H + c] = 0.f;
-        a.T2g[(kb + B + row) * H + c] = 0.f;
+      for (int q = 0; q < nr; ++q) {
+        const long k = kb + row + q * B;
+        if (c < H) {
+          a.T1g[k * H + c] = 0.f;
+          a.T2g[k * H + c] = 0.f;
+        }
+        a.T2in[k * (H + 1) + c] = 0.f;
+        a.T3in[k * (H + 1) + c] = 0.f;
       }
     }
-    for (int idx = tid; idx < PR * din; idx += blockDim.x) {
-      const int r = idx / din, c = idx % din, row = r0 + r;
+    for (int idx = tid; idx < PR * l1; idx += blockDim.x) {
+      const int r = idx / l1, c = idx % l1, row = r0 + r;
       if (row >= B) continue;
-      a.T3g[(kb + row) * din + c] = 0.f;
-      if (CNF) a.T3g[(kb + B + row) * din + c] = 0.f;
+      for (int q = 0; q < nr; ++q) {
+        const long k = kb + row + q * B;
+        a.T1in[k * l1 + c] = 0.f;
+        if (c < din) a.T3g[k * din + c] = 0.f;
+      }
     }
     return;
   }
-  const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
   auto on = [&](int row) { return row < B && a.act[row] == kRunning; };
 
   const float* b1 = a.w.fvec;

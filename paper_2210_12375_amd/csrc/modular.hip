@@ -17,6 +17,7 @@
 // count once per kRoundsPerSync rounds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -120,8 +121,15 @@ struct Back {
   // the current checkpoint segment, kept from its one recomputation so the
   // vector-Jacobian products neither recompute stages nor the forward layers
   // (null: recompute per step).
+  // Two such stores (half 1 at Yst + yst_half, Ast + ast_half): the next
+  // segment's recomputation runs on a second stream while this segment's
+  // vector-Jacobian products run, with its own step view act2, bh2, bt2.
   R* Yst;
   float* Ast;
+  size_t yst_half, ast_half;
+  int32_t* act2;
+  R* bh2;
+  double* bt2;
   long P;
 };
 
@@ -809,6 +817,10 @@ struct ModImpl {
   // private stream for captures (the caller's may be the null stream,
   // which cannot be captured; graphs are replayed on the caller's)
   hipStream_t cap_stream = nullptr;
+  // the discrete adjoint's second stream (segment recomputation) and its
+  // events: start, ready[2], free[2], done
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev[6] = {};
 };
 
 // Captures what enqueue(q) launches on the handle's capture stream q into an
@@ -933,8 +945,13 @@ size_t lay_mod(const bode_config& c, void* base, Mod<R>* m, MfmaWeights* mw,
     const size_t store = (size_t)k * 7 * (B * D * sizeof(R) + Bs * 2 * H * 4);
     if (std::is_same<R, float>::value && uses_mfma(c, din) &&
         store <= (size_t(2) << 30)) {
-      bk.Yst = L.take<R>((size_t)k * 7 * B * D);
-      bk.Ast = L.take<float>((size_t)k * 7 * Bs * 2 * H);
+      bk.yst_half = (size_t)k * 7 * B * D;
+      bk.ast_half = (size_t)k * 7 * Bs * 2 * H;
+      bk.Yst = L.take<R>(2 * bk.yst_half);
+      bk.Ast = L.take<float>(2 * bk.ast_half);
+      bk.act2 = L.take<int32_t>(B);
+      bk.bh2 = L.take<R>(B);
+      bk.bt2 = L.take<double>(B);
     }
   }
   MfmaWeights w{};
@@ -2049,7 +2066,9 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   const dim3 rows_g((m.B + 3) / 4), blk(256);
   hipLaunchKernelGGL(fill_r<R>, lin_grid(b.G * b.P), blk, 0, s, b.slots,
                      (long)b.G * b.P, R(0));
-  {  // tape inputs of tiles no step writes must be finite (they meet 0)
+  if (im.mw.packedT == nullptr) {
+    // tape inputs of tiles no step writes must be finite (they meet 0); the
+    // matrix-core VJP kernels write zeros into those rows themselves
     const long n1 = (long)(m.d_in + 2) * b.K, n2 = (long)(m.H + 1) * b.K;
     hipLaunchKernelGGL(fill_r<R>, lin_grid(n1), blk, 0, s, b.T1in, n1, R(0));
     hipLaunchKernelGGL(fill_r<R>, lin_grid(n2), blk, 0, s, b.T2in, n2, R(0));
@@ -2072,51 +2091,11 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   v.st.status = b.act;
   v.K = b.Ks;
   const int k = b.k;
-  const bool store = b.Yst != nullptr;
-  for (int n = nmax - 1; n >= 0; --n) {
-    const int seg = n / k, base = seg * k;
-    if (store) {
-      if (n == nmax - 1 || n == base + k - 1) {
-        // entering a segment from above: each of its steps base .. n is
-        // evaluated once, its stage inputs and layer values kept
-        hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b,
-                           seg, b.yseg);
-        const size_t BD7 = 7 * (size_t)BD;
-        for (int mm = base; mm <= n; ++mm) {
-          const int j = mm - base;
-          // y_mm: the checkpoint, else stage 7's input of step mm - 1
-          R* ym = j == 0 ? b.yseg : b.Yst + (size_t)(j - 1) * BD7 + 6 * BD;
-          hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
-                             (const R*)ym, b.Yst + (size_t)j * BD7);
-          v.st.y = ym;
-          e = stages_store<R, M>(im, v, b, j, s);
-          if (e != hipSuccess) return e;
-        }
-      }
-      hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
-                         (const R*)nullptr, (R*)nullptr);
-    } else {
-      if (n == nmax - 1 || n == base + k - 1) {
-        // entering a segment from above: states y_base .. y_n by
-        // recomputation
-        hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b,
-                           seg, b.yseg);
-        for (int mm = base; mm < n; ++mm) {
-          R* ym = b.yseg + (size_t)(mm - base) * BD;
-          hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
-                             (const R*)nullptr, (R*)nullptr);
-          v.st.y = ym;
-          e = stages<R, M>(im, v, b, ym + BD, false, s);
-          if (e != hipSuccess) return e;
-        }
-      }
-      R* yn = b.yseg + (size_t)(n - base) * BD;
-      hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
-                         (const R*)yn, b.Ys);
-      v.st.y = yn;
-      e = stages<R, M>(im, v, b, nullptr, true, s);
-      if (e != hipSuccess) return e;
-    }
+  // Step n's cotangent chain: dense-output cotangents, the seven stage
+  // VJPs (on the stored stage inputs Yh and layers Ah of segment step j,
+  // or recomputing), and the chunk's parameter-gradient GEMMs.
+  auto back_step = [&](int n, const R* Yh, const float* Ah,
+                       int j) -> hipError_t {
     hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval);
     // this step's place in its tape chunk (steps are taken in reverse)
     const int slot = (nmax - 1 - n) % b.C;
@@ -2138,21 +2117,20 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       sp.s = st;
       sp.c = M::C[st - 1];
       sp.kbase = kbase;
-      if (store) {
-        const int j = n - base;
-        sp.Y = b.Yst + ((size_t)j * 7 + st - 1) * BD;
-        sp.act_in = b.Ast + ((size_t)j * 7 + st - 1) *
-                                ((size_t)m.B * (m.cnf ? 2 : 1) * 2 * m.H);
+      if (Yh != nullptr) {
+        sp.Y = Yh + ((size_t)j * 7 + st - 1) * BD;
+        sp.act_in = Ah + ((size_t)j * 7 + st - 1) *
+                             ((size_t)m.B * (m.cnf ? 2 : 1) * 2 * m.H);
       }
       // kappa_j receives h a_{s j} mu_s for the stages j < s
       const StageSpec ss = stage_spec<M>(st - 1 > 0 ? st - 1 : 0);
       sp.n = st - 1 > 0 ? ss.n : 0;
-      for (int j = 0; j < sp.n; ++j) {
-        sp.kidx[j] = ss.kidx[j];
-        sp.coef[j] = ss.coef[j];
+      for (int q = 0; q < sp.n; ++q) {
+        sp.kidx[q] = ss.kidx[q];
+        sp.coef[q] = ss.coef[q];
       }
-      e = vjp<R>(im, m, b, sp, s);
-      if (e != hipSuccess) return e;
+      const hipError_t r = vjp<R>(im, m, b, sp, s);
+      if (r != hipSuccess) return r;
     }
     if (slot == b.C - 1 || n == 0) {
       // parameter gradient of the chunk's steps: one GEMM per layer over
@@ -2160,14 +2138,110 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       const long Kc = (long)(slot + 1) * 7 * Bs;
       const int H = m.H, din = m.d_in, n0 = din + 1;
       const long o2 = (long)(n0 + 1) * H, o3 = o2 + (long)(H + 1) * H;
-      e = launch_grad_gemm<R>(b.T1in, b.T1g, Kc, n0 + 1, H, b.G, b.slots,
-                              b.P, 0, s);
-      if (e == hipSuccess)
-        e = launch_grad_gemm<R>(b.T2in, b.T2g, Kc, H + 1, H, b.G, b.slots,
+      hipError_t r = launch_grad_gemm<R>(b.T1in, b.T1g, Kc, n0 + 1, H, b.G,
+                                         b.slots, b.P, 0, s);
+      if (r == hipSuccess)
+        r = launch_grad_gemm<R>(b.T2in, b.T2g, Kc, H + 1, H, b.G, b.slots,
                                 b.P, o2, s);
-      if (e == hipSuccess)
-        e = launch_grad_gemm<R>(b.T3in, b.T3g, Kc, H + 1, din, b.G, b.slots,
+      if (r == hipSuccess)
+        r = launch_grad_gemm<R>(b.T3in, b.T3g, Kc, H + 1, din, b.G, b.slots,
                                 b.P, o3, s);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
+  if (b.Yst != nullptr) {
+    // Segment store, pipelined over two streams: segment q - 1 is
+    // recomputed on the second stream (its stage inputs and layers into
+    // store half (q - 1) & 1) while the caller's stream runs segment q's
+    // cotangent chain on half q & 1.  Both chains are sequences of short
+    // launches on a fraction of the compute units, so they overlap.
+    if (im.aux_stream == nullptr) {
+      e = hipStreamCreateWithFlags(&im.aux_stream, hipStreamNonBlocking);
+      for (hipEvent_t& ev : im.ev)
+        if (e == hipSuccess && ev == nullptr)
+          e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    hipStream_t s2 = im.aux_stream;
+    hipEvent_t *ready = im.ev + 1, *freed = im.ev + 3;
+    e = hipEventRecord(im.ev[0], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, im.ev[0], 0);
+    if (e != hipSuccess) return e;
+    Back<R> br = b;  // the recomputation's own step view
+    br.act = b.act2;
+    br.bh = b.bh2;
+    br.bt = b.bt2;
+    Mod<R> vr = m;
+    vr.hs = br.bh;
+    vr.st.t = br.bt;
+    vr.st.status = br.act;
+    vr.K = b.Ks;
+    const int nseg = (nmax + k - 1) / k;
+    const size_t BD7 = 7 * (size_t)BD;
+    auto seg_top = [&](int q) { return std::min(q * k + k, nmax) - 1; };
+    auto recompute = [&](int q) -> hipError_t {
+      const int half = q & 1;
+      hipError_t r = hipSuccess;
+      // the half was last read by segment q + 2's cotangent chain
+      if (q + 2 < nseg) r = hipStreamWaitEvent(s2, freed[half], 0);
+      if (r != hipSuccess) return r;
+      Back<R> bq = br;
+      bq.Yst = b.Yst + half * b.yst_half;
+      bq.Ast = b.Ast + half * b.ast_half;
+      hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s2, m, bq, q,
+                         b.yseg);
+      for (int mm = q * k; mm <= seg_top(q) && r == hipSuccess; ++mm) {
+        const int j = mm - q * k;
+        // y_mm: the checkpoint, else stage 7's input of step mm - 1
+        R* ym = j == 0 ? b.yseg : bq.Yst + (size_t)(j - 1) * BD7 + 6 * BD;
+        hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s2, m, bq, mm,
+                           (const R*)ym, bq.Yst + (size_t)j * BD7);
+        vr.st.y = ym;
+        r = stages_store<R, M>(im, vr, bq, j, s2);
+      }
+      if (r == hipSuccess) r = hipEventRecord(ready[half], s2);
+      return r;
+    };
+    if (nseg > 0) e = recompute(nseg - 1);
+    for (int q = nseg - 1; q >= 0 && e == hipSuccess; --q) {
+      if (q > 0) e = recompute(q - 1);  // enqueued ahead of q's chain
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ready[q & 1], 0);
+      const R* Yh = b.Yst + (q & 1) * b.yst_half;
+      const float* Ah = b.Ast + (q & 1) * b.ast_half;
+      for (int n = seg_top(q); n >= q * k && e == hipSuccess; --n) {
+        hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
+                           (const R*)nullptr, (R*)nullptr);
+        e = back_step(n, Yh, Ah, n - q * k);
+      }
+      if (e == hipSuccess) e = hipEventRecord(freed[q & 1], s);
+    }
+    if (e == hipSuccess) e = hipEventRecord(im.ev[5], s2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, im.ev[5], 0);
+    if (e != hipSuccess) return e;
+  } else {
+    for (int n = nmax - 1; n >= 0; --n) {
+      const int seg = n / k, base = seg * k;
+      if (n == nmax - 1 || n == base + k - 1) {
+        // entering a segment from above: states y_base .. y_n by
+        // recomputation
+        hipLaunchKernelGGL(adj_load_ckpt<R>, lin_grid(BD), blk, 0, s, m, b,
+                           seg, b.yseg);
+        for (int mm = base; mm < n; ++mm) {
+          R* ym = b.yseg + (size_t)(mm - base) * BD;
+          hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, mm,
+                             (const R*)nullptr, (R*)nullptr);
+          v.st.y = ym;
+          e = stages<R, M>(im, v, b, ym + BD, false, s);
+          if (e != hipSuccess) return e;
+        }
+      }
+      R* yn = b.yseg + (size_t)(n - base) * BD;
+      hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
+                         (const R*)yn, b.Ys);
+      v.st.y = yn;
+      e = stages<R, M>(im, v, b, nullptr, true, s);
+      if (e == hipSuccess) e = back_step(n, nullptr, nullptr, 0);
       if (e != hipSuccess) return e;
     }
   }
@@ -2276,6 +2350,9 @@ void modular_release(ModularPlan& mp) {
   if (im->host_running) (void)hipHostFree(im->host_running);
   if (im->rounds_exec) (void)hipGraphExecDestroy(im->rounds_exec);
   if (im->cap_stream) (void)hipStreamDestroy(im->cap_stream);
+  if (im->aux_stream) (void)hipStreamDestroy(im->aux_stream);
+  for (hipEvent_t& e : im->ev)
+    if (e) (void)hipEventDestroy(e);
   delete im;
   mp.impl = nullptr;
 }
