@@ -87,6 +87,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   typedef typename Op::W W;
   constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 16 * WV,
                 SA = H + Op::kPad;
+  // weight blocks in flight: two for the CNF, whose kernel is held to 128
+  // registers (four wavefronts per SIMD)
+  constexpr int PD = CNF ? 2 : mtile::ring_depth(NTW, Op::kFragRegs),
+                PD4 = CNF ? 2 : mtile::ring_depth(4, Op::kFragRegs);
   const int din = a.din, D = a.D, B = a.B;
   const Dims dm = dims(din, H);
   const DimsT dt = dims_t(din, H);
@@ -98,13 +102,17 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   float* tcol = reinterpret_cast<float*>(Ah + Op::kPlanes * PA);  // [PR]
   float* MU = reinterpret_cast<float*>(Xh);  // [PR][din], after S2 is read
   __shared__ int any_running;
+  __shared__ int onr[PR];  // the tile's rows that have this step
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = blockIdx.x * PR;
   if (tid == 0) any_running = 0;
   __syncthreads();
-  if (tid < PR && r0 + tid < B && a.act[r0 + tid] == kRunning)
-    any_running = 1;
+  if (tid < PR) {
+    const int o = r0 + tid < B && a.act[r0 + tid] == kRunning;
+    onr[tid] = o;
+    if (o) any_running = 1;
+  }
   __syncthreads();
   const long kb = a.kb;
   const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
@@ -137,7 +145,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
     }
     return;
   }
-  auto on = [&](int row) { return row < B && a.act[row] == kRunning; };
+  auto on = [&](int row) { return onr[row - r0] != 0; };  // row in the tile
 
   const float* b1 = a.w.fvec;
   const float* w1t = b1 + H;
@@ -158,20 +166,20 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
     // input, cotangent, probe, stored layers, time) before the first store.
     constexpr int NE = (PR * 256 + 64 * WV - 1) / (64 * WV);
     float Yr[NE], Kz[NE], Er[NE], Kl[NE];
+    // (loads at clamped rows, unconditionally, so none waits on a branch;
+    // rows without this step are then read as zero: their stored values
+    // come from stale states)
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const int idx = tid + e * (int)blockDim.x;
-      Yr[e] = Kz[e] = Er[e] = Kl[e] = 0.f;
-      if (idx < PR * din) {
-        const int r = idx / din, c = idx % din, row = r0 + r;
-        if (on(row)) {
-          Yr[e] = a.Y[(long)row * D + c];
-          Kz[e] = a.kap_s[(long)row * D + c];
-          if (CNF) {
-            Er[e] = a.eps[(long)row * D + c];
-            Kl[e] = a.kap_s[(long)row * D + din];
-          }
-        }
+      const int ii = idx < PR * din ? idx : 0;
+      const int r = ii / din, c = ii % din;
+      const long o = (long)(r0 + r < B ? r0 + r : B - 1) * D;
+      Yr[e] = a.Y[o + c];
+      Kz[e] = a.kap_s[o + c];
+      if (CNF) {
+        Er[e] = a.eps[o + c];
+        Kl[e] = a.kap_s[o + din];
       }
     }
 #pragma unroll
@@ -184,17 +192,28 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
           const int row = rq + i;
           const bool primal = !CNF || row < PR;
           const int g = r0 + (primal ? row : row - PR);
-          // rows without this step read as zero (their stored values come
-          // from stale states)
           keep[layer][t][i] =
-              g < B && a.act[g] == kRunning
-                  ? a.act_in[((long)(g + (primal ? 0 : B)) * 2 + layer) * H +
-                             n]
-                  : 0.f;
+              a.act_in[((long)((g < B ? g : B - 1) + (primal ? 0 : B)) * 2 +
+                        layer) * H + n];
         }
       }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int idx = tid + e * (int)blockDim.x;
+      if (idx < PR * din && !onr[idx / din]) Yr[e] = Kz[e] = Er[e] = Kl[e] = 0.f;
+    }
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = rq + i;
+          const int pr = !CNF || row < PR ? row : row - PR;
+          if (r0 + pr >= B || !onr[pr]) keep[layer][t][i] = 0.f;
+        }
     float tv = 0.f;
-    if (tid < PR && on(r0 + tid))
+    if (tid < PR && r0 + tid < B && onr[tid])
       tv = float(a.bt[r0 + tid] + a.c * double(a.bh[r0 + tid]));
     // layer-1 inputs and the cotangent gbar (kappa_z on primal rows,
     // -kappa_l eps on tangent rows) into the tape; gbar into LDS
@@ -302,10 +321,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 0)
-      Op::template gemm<1, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
+      Op::template gemm<1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
                    NTW, lane);
     else
-      Op::template gemm<1, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
+      Op::template gemm<1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
                    wave * NTW, 1, NTW, lane);
     __syncthreads();
     const float* bias = layer == 0 ? b1 : b2;
@@ -369,10 +388,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 1)
-      Op::template gemm<1, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packedT), dt.nk3, dt.nn3, wave * NTW, 1,
+      Op::template gemm<1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packedT), dt.nk3, dt.nn3, wave * NTW, 1,
                    NTW, lane);
     else
-      Op::template gemm<1, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off2, dt.nk2, dt.nn2,
+      Op::template gemm<1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off2, dt.nk2, dt.nn2,
                    wave * NTW, 1, NTW, lane);
     __syncthreads();
     float* Tg = layer == 1 ? a.T2g : a.T1g;
@@ -409,7 +428,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
-      Op::template gemm<1, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
+      Op::template gemm<1, 4, PD4, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
                  WV, ntiles, lane);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -424,25 +443,50 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   }
   __syncthreads();
 
-  // row updates (or, for the continuous adjoint, mu itself)
-  for (int idx = tid; idx < PR * D; idx += blockDim.x) {
-    const int r = idx / D, c = idx % D, row = r0 + r;
-    if (!on(row)) continue;
-    if (a.mu_out != nullptr) {
-      a.mu_out[(long)row * D + c] = c < din ? MU[r * din + c] : 0.f;
-      continue;
+  // row updates (or, for the continuous adjoint, mu itself), NU elements
+  // a thread at a time: every value they read is loaded before any is
+  // written (they write distinct addresses, which the compiler cannot
+  // know, so it would otherwise wait for each load in turn)
+  constexpr int NU = CNF ? 1 : 2;
+  for (int i0 = tid; i0 < PR * D; i0 += NU * (int)blockDim.x) {
+    float lam[NU], lamn[NU], kp[NU][6], h[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int idx = i0 + u * (int)blockDim.x;
+      const int r = idx / D, c = idx % D, row = r0 + r;
+      if (idx >= PR * D || !on(row) || a.mu_out != nullptr) continue;
+      const long o = (long)row * D + c;
+      h[u] = a.bh[row];
+      lam[u] = a.lam[o];
+      lamn[u] = a.lamn[o];
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (j < a.n) kp[u][j] = a.kap[((long)a.kidx[j] * B + row) * D + c];
     }
-    const float h = a.bh[row];
-    float mu = c < din ? MU[r * din + c] : 0.f;
-    const long o = (long)row * D + c;
-    if (a.s == 7) {
-      mu = a.lam[o] + mu;  // Lambda
-      a.lam[o] = mu;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int idx = i0 + u * (int)blockDim.x;
+      const int r = idx / D, c = idx % D, row = r0 + r;
+      if (idx >= PR * D || !on(row)) continue;
+      const long o = (long)row * D + c;
+      float mu = c < din ? MU[r * din + c] : 0.f;
+      if (a.mu_out != nullptr) {
+        a.mu_out[o] = mu;
+        continue;
+      }
+      if (a.s == 7) {
+        mu = lam[u] + mu;  // Lambda
+        a.lam[o] = mu;
+      }
+      const float ln = lamn[u] + mu;
+      a.lamn[o] = ln;
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (j < a.n)
+          a.kap[((long)a.kidx[j] * B + row) * D + c] =
+              kp[u][j] + h[u] * a.coef[j] * mu;
+      if (a.s == 1) a.lam[o] = ln;
     }
-    a.lamn[o] += mu;
-    for (int j = 0; j < a.n; ++j)
-      a.kap[((long)a.kidx[j] * B + row) * D + c] += h * a.coef[j] * mu;
-    if (a.s == 1) a.lam[o] = a.lamn[o];
   }
 }
 

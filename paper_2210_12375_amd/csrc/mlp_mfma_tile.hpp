@@ -122,61 +122,103 @@ __device__ __forceinline__ float fast_tanh(float x) {
   return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
 }
 
+// k blocks of weight fragments a gemm keeps in flight: about 64 registers
+// of ring (regs: registers per fragment), between 2 and 8 blocks.
+constexpr int ring_depth(int ntw, int regs) {
+  return 64 / (ntw * regs) < 2 ? 2 : (64 / (ntw * regs) > 8 ? 8 : 64 / (ntw * regs));
+}
+
+struct f32x8 {
+  f32x4 lo, hi;
+};
+
+// The k loop of a tile product over nk blocks of 32, with the weight
+// fragments of the next P blocks in flight in a ring of registers (a
+// block's L2 latency overlaps the products of the P - 1 blocks before it).
+// load(kb, t) fetches column tile t's fragment of block kb; body(kb, b)
+// issues block kb's products.  Every load is unconditional (tiles past
+// ntiles and blocks past the last re-read valid fragments), so the compiler
+// waits for each fragment exactly when it is used.  NK > 0: nk is the
+// compile-time NK and the loop is unrolled whole.
+template <int NTW, int P, int NK, class F, class Load, class Body>
+__device__ __forceinline__ void ring_gemm(int nk, int ntiles, Load load,
+                                          Body body) {
+  constexpr int PP = NK > 0 && NK < P ? NK : P;
+  const int n = NK > 0 ? NK : nk;
+  F ring[PP][NTW];
+  auto fill = [&](F(&d)[NTW], int kb) {
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) d[t] = load(kb, t < ntiles ? t : 0);
+    // keep the loads where they are issued: the scheduler would otherwise
+    // sink them next to their use and serialize the L2 round trips
+    if constexpr (P > 2) __builtin_amdgcn_sched_barrier(0);
+  };
+#pragma unroll
+  for (int p = 0; p < PP; ++p) fill(ring[p], p < n ? p : n - 1);
+  if constexpr (NK > 0) {
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+      body(kb, ring[kb % PP]);
+      if (kb + PP < NK) fill(ring[kb % PP], kb + PP);
+    }
+  } else {
+    for (int k0 = 0; k0 < n; k0 += PP) {
+#pragma unroll
+      for (int p = 0; p < PP; ++p) {
+        const int kb = k0 + p;
+        if (kb >= n) break;
+        body(kb, ring[p]);
+        fill(ring[p], kb + PP < n ? kb + PP : n - 1);
+      }
+    }
+  }
+}
+
 struct Bf3 {
   typedef uint16_t W;  // packed weight element
   typedef uint16_t A;  // LDS activation element
-  static constexpr int kPlanes = 3, kPad = 8;
+  static constexpr int kPlanes = 3, kPad = 8, kFragRegs = 4;
   __device__ static __forceinline__ void put(A* p, int plane, int off,
                                              float v) {
     put_split(p, plane, off, v);
   }
   // C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
   // B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit
-  // at Ah, Ah + plane, Ah + 2 plane.
-  template <int MT, int NTW>
+  // at Ah, Ah + plane, Ah + 2 plane.  P: k blocks of weights in flight.
+  template <int MT, int NTW, int P = ring_depth(NTW, kFragRegs), int NK = 0>
   __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
                                               const A* Ah, int plane, int lda,
                                               const W* Bp, int nk, int nn,
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    // the weight fragments of k block kb + 1 are requested before the
-    // products of block kb, so the L2 latency of one block overlaps the
-    // matrix work of the previous one
-    bf16x8 bfrag[NTW], bnext[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t)
-      if (t < ntiles)
-        bfrag[t] = gld8(Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8);
-    for (int kb = 0; kb < nk; ++kb) {
-      bf16x8 ah[MT], am[MT], al[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int off = (mt * 16 + r) * lda + kb * 32 + kq;
-        ah[mt] = lds8(Ah + off);
-        am[mt] = lds8(Ah + plane + off);
-        al[mt] = lds8(Ah + 2 * plane + off);
-      }
-      const int kn = kb + 1 < nk ? kb + 1 : kb;
-#pragma unroll
-      for (int t = 0; t < NTW; ++t)
-        if (t < ntiles)
-          bnext[t] =
-              gld8(Bp + ((size_t)(kn * nn + nb0 + t * nstep) * 64 + lane) * 8);
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        if (t < ntiles) {
+    ring_gemm<NTW, P, NK, bf16x8>(
+        nk, ntiles,
+        [&](int kb, int t) {
+          return gld8(Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) *
+                               8);
+        },
+        [&](int kb, const bf16x8(&b)[NTW]) {
+          bf16x8 ah[MT], am[MT], al[MT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            acc[mt][t] = mfma(al[mt], bfrag[t], acc[mt][t]);
-            acc[mt][t] = mfma(am[mt], bfrag[t], acc[mt][t]);
-            acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
+            const int off = (mt * 16 + r) * lda + kb * 32 + kq;
+            ah[mt] = lds8(Ah + off);
+            am[mt] = lds8(Ah + plane + off);
+            al[mt] = lds8(Ah + 2 * plane + off);
           }
-        }
-      }
 #pragma unroll
-      for (int t = 0; t < NTW; ++t) bfrag[t] = bnext[t];
-    }
+          for (int t = 0; t < NTW; ++t) {
+            if (t < ntiles) {
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                acc[mt][t] = mfma(al[mt], b[t], acc[mt][t]);
+                acc[mt][t] = mfma(am[mt], b[t], acc[mt][t]);
+                acc[mt][t] = mfma(ah[mt], b[t], acc[mt][t]);
+              }
+            }
+          }
+        });
   }
 };
 
@@ -187,42 +229,35 @@ struct Bf3 {
 struct Bf1 {
   typedef uint16_t W;
   typedef uint16_t A;
-  static constexpr int kPlanes = 1, kPad = 8;
+  static constexpr int kPlanes = 1, kPad = 8, kFragRegs = 4;
   __device__ static __forceinline__ void put(A* p, int, int off, float v) {
     p[off] = f2bf(v);
   }
-  template <int MT, int NTW>
+  template <int MT, int NTW, int P = ring_depth(NTW, kFragRegs), int NK = 0>
   __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
                                               const A* Ah, int, int lda,
                                               const W* Bp, int nk, int nn,
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    bf16x8 bfrag[NTW], bnext[NTW];  // next block's weights in flight
-#pragma unroll
-    for (int t = 0; t < NTW; ++t)
-      if (t < ntiles)
-        bfrag[t] = gld8(Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8);
-    for (int kb = 0; kb < nk; ++kb) {
-      bf16x8 ah[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-        ah[mt] = lds8(Ah + (mt * 16 + r) * lda + kb * 32 + kq);
-      const int kn = kb + 1 < nk ? kb + 1 : kb;
-#pragma unroll
-      for (int t = 0; t < NTW; ++t)
-        if (t < ntiles)
-          bnext[t] = gld8(Bp + ((size_t)(kn * nn + nb0 + t * nstep) * 64 +
-                                lane) * 8);
-#pragma unroll
-      for (int t = 0; t < NTW; ++t)
-        if (t < ntiles)
+    ring_gemm<NTW, P, NK, bf16x8>(
+        nk, ntiles,
+        [&](int kb, int t) {
+          return gld8(Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) *
+                               8);
+        },
+        [&](int kb, const bf16x8(&b)[NTW]) {
+          bf16x8 ah[MT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
-            acc[mt][t] = mfma(ah[mt], bfrag[t], acc[mt][t]);
+            ah[mt] = lds8(Ah + (mt * 16 + r) * lda + kb * 32 + kq);
 #pragma unroll
-      for (int t = 0; t < NTW; ++t) bfrag[t] = bnext[t];
-    }
+          for (int t = 0; t < NTW; ++t)
+            if (t < ntiles)
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt)
+                acc[mt][t] = mfma(ah[mt], b[t], acc[mt][t]);
+        });
   }
 };
 
@@ -232,67 +267,50 @@ struct Bf1 {
 struct F32 {
   typedef float W;
   typedef float A;
-  static constexpr int kPlanes = 1, kPad = 4;
+  static constexpr int kPlanes = 1, kPad = 4, kFragRegs = 8;
   __device__ static __forceinline__ void put(A* p, int, int off, float v) {
     p[off] = v;
   }
-  template <int MT, int NTW>
+  template <int MT, int NTW, int P = ring_depth(NTW, kFragRegs), int NK = 0>
   __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
                                               const A* Ah, int, int lda,
                                               const W* Bp, int nk, int nn,
                                               int nb0, int nstep, int ntiles,
                                               int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    // next k block's weight fragments in flight during this block's products
-    f32x4 b0[NTW], b1[NTW], n0[NTW], n1[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-      if (t < ntiles) {
-        const W* q = Bp + ((size_t)(nb0 + t * nstep) * 64 + lane) * 8;
-        b0[t] = *reinterpret_cast<const f32x4*>(q);
-        b1[t] = *reinterpret_cast<const f32x4*>(q + 4);
-      }
-    }
-    for (int kb = 0; kb < nk; ++kb) {
-      f32x4 a0[MT], a1[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const A* p = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
-        a0[mt] = *reinterpret_cast<const f32x4*>(p);
-        a1[mt] = *reinterpret_cast<const f32x4*>(p + 4);
-      }
-      const int kn = kb + 1 < nk ? kb + 1 : kb;
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        if (t < ntiles) {
+    ring_gemm<NTW, P, NK, f32x8>(
+        nk, ntiles,
+        [&](int kb, int t) {
           const W* q =
-              Bp + ((size_t)(kn * nn + nb0 + t * nstep) * 64 + lane) * 8;
-          n0[t] = *reinterpret_cast<const f32x4*>(q);
-          n1[t] = *reinterpret_cast<const f32x4*>(q + 4);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        if (t < ntiles) {
+              Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) * 8;
+          return f32x8{*reinterpret_cast<const f32x4*>(q),
+                       *reinterpret_cast<const f32x4*>(q + 4)};
+        },
+        [&](int kb, const f32x8(&b)[NTW]) {
+          f32x4 a0[MT], a1[MT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  a0[mt][q], b0[t][q], acc[mt][t], 0, 0, 0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  a1[mt][q], b1[t][q], acc[mt][t], 0, 0, 0);
+            const A* q = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
+            a0[mt] = *reinterpret_cast<const f32x4*>(q);
+            a1[mt] = *reinterpret_cast<const f32x4*>(q + 4);
           }
-        }
-      }
 #pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        b0[t] = n0[t];
-        b1[t] = n1[t];
-      }
-    }
+          for (int t = 0; t < NTW; ++t) {
+            if (t < ntiles) {
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                  acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                      a0[mt][q], b[t].lo[q], acc[mt][t], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                  acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                      a1[mt][q], b[t].hi[q], acc[mt][t], 0, 0, 0);
+              }
+            }
+          }
+        });
   }
 };
 
@@ -300,7 +318,11 @@ struct F32 {
 // instances; CNF: 8 instances and their 8 tangent rows), by a workgroup of
 // WV wavefronts; NTW = H / (16 WV) column tiles per wavefront in the hidden
 // layers.  smem_raw: mfma_smem<Op, NTW, CNF, WV>(din) bytes of LDS.
-template <class Op, int NTW, bool CNF, int WV>
+// DEEP: several k blocks of weights in flight (ring_depth) and the layer
+// values stored to a.act_out when it is set; otherwise two blocks and no
+// layer store, which keeps the persistent solve kernels (the field, the
+// error norm and the controller in one body) within their registers.
+template <class Op, int NTW, bool CNF, int WV, bool DEEP = true>
 __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
                                            unsigned char* smem_raw) {
   constexpr int MT = 1;
@@ -310,6 +332,9 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   constexpr int PR = CNF ? 8 : RT;  // instances per workgroup
   constexpr int H = NTW * 16 * WV;
   constexpr int SA = H + Op::kPad;  // LDS row stride (bank spread)
+  constexpr int PH = DEEP ? ring_depth(NTW, Op::kFragRegs) : 2,
+                P4 = DEEP ? ring_depth(4, Op::kFragRegs) : 2,
+                NKH = DEEP ? H / 32 : 0;
   const int din = a.din, D = a.D, B = a.B;
   const Dims dm = dims(din, H);
   const int SX = dm.K1 + Op::kPad;
@@ -371,14 +396,26 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int t = 0; t < NTW; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the layer's bias (and time weight) at this lane's columns, requested
+    // ahead of the products: in the epilogue they would be re-read after
+    // every store that might alias them
+    float bn[NTW], wn[NTW];
+    if constexpr (DEEP) {
+      const float* bias = layer == 0 ? b1 : b2;
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int n = (wave * NTW + t) * 16 + col;
+        bn[t] = bias[n];
+        wn[t] = layer == 0 ? w1t[n] : 0.f;
+      }
+    }
     if (layer == 0)
-      Op::template gemm<MT, NTW>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
+      Op::template gemm<MT, NTW, PH>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
                     NTW, lane);
     else
-      Op::template gemm<MT, NTW>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
+      Op::template gemm<MT, NTW, PH, NKH>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
                     wave * NTW, 1, NTW, lane);
     __syncthreads();  // every wave has read its layer input
-    const float* bias = layer == 0 ? b1 : b2;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -390,8 +427,13 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
           float v = acc[mt][t][i];
           const bool primal = !CNF || row < PR;
           if (primal) {
-            v += bias[n];
-            if (layer == 0) v += tcol[row] * w1t[n];
+            if constexpr (DEEP) {
+              v += bn[t];
+              if (layer == 0) v += tcol[row] * wn[t];
+            } else {
+              v += (layer == 0 ? b1 : b2)[n];
+              if (layer == 0) v += tcol[row] * w1t[n];
+            }
           }
           float act = primal ? fast_tanh(v) : 0.f;
           if (CNF) {
@@ -399,7 +441,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
             if (!primal) act = (1.f - ap * ap) * v;
           }
           Op::put(Ah, PA, row * SA + n, act);
-          if (a.act_out != nullptr) {
+          if (DEEP && a.act_out != nullptr) {
             const int g = r0 + (primal ? row : row - PR);
             if (g < B)
               a.act_out[((long)(g + (primal ? 0 : B)) * 2 + layer) * H + n] =
@@ -418,8 +460,25 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // output bias and (CNF tangent rows, DEEP) probe values, ahead of the
+    // products
+    float b3n[4], ep[MT][4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int n = (wave + WV * t) * 16 + col;
+      b3n[t] = t < ntiles ? b3[n] : 0.f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = mt * 16 + rq + i, row = r0 + r - PR;
+          ep[mt][t][i] = DEEP && CNF && t < ntiles && r >= PR && row < B
+                             ? a.eps[(long)row * D + n]
+                             : 0.f;
+        }
+    }
     if (ntiles > 0)
-      Op::template gemm<MT, 4>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off3, dm.nk3, dm.nn3, wave,
+      Op::template gemm<MT, 4, P4, NKH>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off3, dm.nk3, dm.nn3, wave,
                   WV, ntiles, lane);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -434,11 +493,12 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
           const float v = acc[mt][t][i];
           if (!CNF || r < PR) {
             const int row = r0 + r;
-            if (row < B) a.out[(long)row * D + n] = v + b3[n];
+            if (row < B) a.out[(long)row * D + n] = v + b3n[t];
           } else {
             // tangent row: eps_n * (dg/dz eps)_n, summed over the 16 columns
             const int pr = r - PR, row = r0 + pr;
-            float q = row < B ? a.eps[(long)row * D + n] * v : 0.f;
+            float q = DEEP ? ep[mt][t][i] * v
+                           : (row < B ? a.eps[(long)row * D + n] * v : 0.f);
             q += __shfl_xor(q, 1, 64);
             q += __shfl_xor(q, 2, 64);
             q += __shfl_xor(q, 4, 64);

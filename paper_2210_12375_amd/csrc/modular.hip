@@ -724,7 +724,7 @@ __global__ __launch_bounds__(64 * WV) void solve_fused_kernel(Mod<float> m,
     __syncthreads();
     if (!active) break;
     for (int s = 0; s < 6; ++s) {
-      mtile::field_tile<Op, NTW, CNF, WV>(f.st[s], r0, smem_raw);
+      mtile::field_tile<Op, NTW, CNF, WV, false>(f.st[s], r0, smem_raw);
       __syncthreads();
     }
     // MLP: two rows per wavefront (32 lanes each) while D fits two columns
