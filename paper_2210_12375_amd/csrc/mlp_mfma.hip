@@ -321,10 +321,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 0)
-      Op::template gemm<1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
+      gemm<Op, 1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
                    NTW, lane);
     else
-      Op::template gemm<1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
+      gemm<Op, 1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
                    wave * NTW, 1, NTW, lane);
     __syncthreads();
     const float* bias = layer == 0 ? b1 : b2;
@@ -388,10 +388,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 1)
-      Op::template gemm<1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packedT), dt.nk3, dt.nn3, wave * NTW, 1,
+      gemm<Op, 1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packedT), dt.nk3, dt.nn3, wave * NTW, 1,
                    NTW, lane);
     else
-      Op::template gemm<1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off2, dt.nk2, dt.nn2,
+      gemm<Op, 1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off2, dt.nk2, dt.nn2,
                    wave * NTW, 1, NTW, lane);
     __syncthreads();
     float* Tg = layer == 1 ? a.T2g : a.T1g;
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (ntiles > 0)
-      Op::template gemm<1, 4, PD4, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
+      gemm<Op, 1, 4, PD4, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
                  WV, ntiles, lane);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {

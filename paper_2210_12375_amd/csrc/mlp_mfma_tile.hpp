@@ -122,8 +122,8 @@ __device__ __forceinline__ float fast_tanh(float x) {
   return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
 }
 
-// k blocks of weight fragments a gemm keeps in flight: about 64 registers
-// of ring (regs: registers per fragment), between 2 and 8 blocks.
+// k blocks of weight fragments a product keeps in flight: about 64
+// registers of ring (regs: registers per fragment), between 2 and 8 blocks.
 constexpr int ring_depth(int ntw, int regs) {
   return 64 / (ntw * regs) < 2 ? 2 : (64 / (ntw * regs) > 8 ? 8 : 64 / (ntw * regs));
 }
@@ -132,93 +132,107 @@ struct f32x8 {
   f32x4 lo, hi;
 };
 
-// The k loop of a tile product over nk blocks of 32, with the weight
-// fragments of the next P blocks in flight in a ring of registers (a
-// block's L2 latency overlaps the products of the P - 1 blocks before it).
-// load(kb, t) fetches column tile t's fragment of block kb; body(kb, b)
-// issues block kb's products.  Every load is unconditional (tiles past
-// ntiles and blocks past the last re-read valid fragments), so the compiler
-// waits for each fragment exactly when it is used.  NK > 0: nk is the
-// compile-time NK and the loop is unrolled whole.
-template <int NTW, int P, int NK, class F, class Load, class Body>
-__device__ __forceinline__ void ring_gemm(int nk, int ntiles, Load load,
-                                          Body body) {
-  constexpr int PP = NK > 0 && NK < P ? NK : P;
-  const int n = NK > 0 ? NK : nk;
-  F ring[PP][NTW];
-  auto fill = [&](F(&d)[NTW], int kb) {
+// Weight fragments of the next P k blocks of a tile product (NK > 0: the
+// product has NK blocks, known at compile time), held in registers.
+template <class F, int NTW, int P, int NK>
+struct Ring {
+  static constexpr int kP = NK > 0 && NK < P ? NK : P, kNK = NK;
+  F f[kP][NTW];
+};
+
+// Requests the ring's first blocks.  Called ahead of the product (at the
+// start of the layer before, say), so their L2 latency overlaps other work.
+template <int NTW, class R, class Load>
+__device__ __forceinline__ void ring_start(R& r, int nk, int ntiles,
+                                           Load load) {
+  const int n = R::kNK > 0 ? R::kNK : nk;
+#pragma unroll
+  for (int p = 0; p < R::kP; ++p)
+    if (p < n)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t)
+        r.f[p][t] = load(p, t < ntiles ? t : 0);
+  if constexpr (R::kP > 2) __builtin_amdgcn_sched_barrier(0);
+}
+
+// The k loop over nk blocks of 32: block kb's products (body), then block
+// kb + kP requested into the registers block kb used (a block's L2 latency
+// overlaps the products of the kP - 1 blocks before it).  The refills are
+// unconditional (blocks past the last re-read valid fragments), so the
+// compiler waits for each fragment exactly when it is used; the scheduler
+// is kept from sinking them next to their use.
+template <int NTW, class R, class Load, class Body>
+__device__ __forceinline__ void ring_run(R& r, int nk, int ntiles, Load load,
+                                         Body body) {
+  constexpr int PP = R::kP;
+  auto fill = [&](auto& d, int kb) {
 #pragma unroll
     for (int t = 0; t < NTW; ++t) d[t] = load(kb, t < ntiles ? t : 0);
-    // keep the loads where they are issued: the scheduler would otherwise
-    // sink them next to their use and serialize the L2 round trips
-    if constexpr (P > 2) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (PP > 2) __builtin_amdgcn_sched_barrier(0);
   };
+  if constexpr (R::kNK > 0) {
 #pragma unroll
-  for (int p = 0; p < PP; ++p) fill(ring[p], p < n ? p : n - 1);
-  if constexpr (NK > 0) {
-#pragma unroll
-    for (int kb = 0; kb < NK; ++kb) {
-      body(kb, ring[kb % PP]);
-      if (kb + PP < NK) fill(ring[kb % PP], kb + PP);
+    for (int kb = 0; kb < R::kNK; ++kb) {
+      body(kb, r.f[kb % PP]);
+      if (kb + PP < R::kNK) fill(r.f[kb % PP], kb + PP);
     }
   } else {
-    for (int k0 = 0; k0 < n; k0 += PP) {
+    for (int k0 = 0; k0 < nk; k0 += PP) {
 #pragma unroll
       for (int p = 0; p < PP; ++p) {
         const int kb = k0 + p;
-        if (kb >= n) break;
-        body(kb, ring[p]);
-        fill(ring[p], kb + PP < n ? kb + PP : n - 1);
+        if (kb >= nk) break;
+        body(kb, r.f[p]);
+        fill(r.f[p], kb + PP < nk ? kb + PP : nk - 1);
       }
     }
   }
 }
 
+// Operand policies.  Each has a fragment type Frag (one lane's share of a
+// 32 x 16 weight block), frag() to load one, and block() to issue the
+// products of one k block of 32 for MT 16-row tiles and NTW column tiles.
+
 struct Bf3 {
   typedef uint16_t W;  // packed weight element
   typedef uint16_t A;  // LDS activation element
+  typedef bf16x8 Frag;
   static constexpr int kPlanes = 3, kPad = 8, kFragRegs = 4;
   __device__ static __forceinline__ void put(A* p, int plane, int off,
                                              float v) {
     put_split(p, plane, off, v);
   }
-  // C[MT][NTW] += A(LDS hi + mid + lo, MT 16-row tiles, K = 32 nk) x
-  // B(packed, columns of n-tiles nb0 + t * nstep).  The three A terms sit
-  // at Ah, Ah + plane, Ah + 2 plane.  P: k blocks of weights in flight.
-  template <int MT, int NTW, int P = ring_depth(NTW, kFragRegs), int NK = 0>
-  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
-                                              const A* Ah, int plane, int lda,
-                                              const W* Bp, int nk, int nn,
-                                              int nb0, int nstep, int ntiles,
-                                              int lane) {
+  __device__ static __forceinline__ Frag frag(const W* Bp, long f, int lane) {
+    return gld8(Bp + (f * 64 + lane) * 8);
+  }
+  // C[MT][NTW] += A(LDS hi + mid + lo at Ah, Ah + plane, Ah + 2 plane;
+  // columns kb * 32 ..) x B(block kb of the column tiles)
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void block(f32x4 (&acc)[MT][NTW],
+                                               const A* Ah, int plane,
+                                               int lda, int kb,
+                                               const Frag (&b)[NTW],
+                                               int ntiles, int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    ring_gemm<NTW, P, NK, bf16x8>(
-        nk, ntiles,
-        [&](int kb, int t) {
-          return gld8(Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) *
-                               8);
-        },
-        [&](int kb, const bf16x8(&b)[NTW]) {
-          bf16x8 ah[MT], am[MT], al[MT];
+    bf16x8 ah[MT], am[MT], al[MT];
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const int off = (mt * 16 + r) * lda + kb * 32 + kq;
-            ah[mt] = lds8(Ah + off);
-            am[mt] = lds8(Ah + plane + off);
-            al[mt] = lds8(Ah + 2 * plane + off);
-          }
+    for (int mt = 0; mt < MT; ++mt) {
+      const int off = (mt * 16 + r) * lda + kb * 32 + kq;
+      ah[mt] = lds8(Ah + off);
+      am[mt] = lds8(Ah + plane + off);
+      al[mt] = lds8(Ah + 2 * plane + off);
+    }
 #pragma unroll
-          for (int t = 0; t < NTW; ++t) {
-            if (t < ntiles) {
+    for (int t = 0; t < NTW; ++t) {
+      if (t < ntiles) {
 #pragma unroll
-              for (int mt = 0; mt < MT; ++mt) {
-                acc[mt][t] = mfma(al[mt], b[t], acc[mt][t]);
-                acc[mt][t] = mfma(am[mt], b[t], acc[mt][t]);
-                acc[mt][t] = mfma(ah[mt], b[t], acc[mt][t]);
-              }
-            }
-          }
-        });
+        for (int mt = 0; mt < MT; ++mt) {
+          acc[mt][t] = mfma(al[mt], b[t], acc[mt][t]);
+          acc[mt][t] = mfma(am[mt], b[t], acc[mt][t]);
+          acc[mt][t] = mfma(ah[mt], b[t], acc[mt][t]);
+        }
+      }
+    }
   }
 };
 
@@ -229,35 +243,30 @@ struct Bf3 {
 struct Bf1 {
   typedef uint16_t W;
   typedef uint16_t A;
+  typedef bf16x8 Frag;
   static constexpr int kPlanes = 1, kPad = 8, kFragRegs = 4;
   __device__ static __forceinline__ void put(A* p, int, int off, float v) {
     p[off] = f2bf(v);
   }
-  template <int MT, int NTW, int P = ring_depth(NTW, kFragRegs), int NK = 0>
-  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
-                                              const A* Ah, int, int lda,
-                                              const W* Bp, int nk, int nn,
-                                              int nb0, int nstep, int ntiles,
-                                              int lane) {
+  __device__ static __forceinline__ Frag frag(const W* Bp, long f, int lane) {
+    return gld8(Bp + (f * 64 + lane) * 8);
+  }
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void block(f32x4 (&acc)[MT][NTW],
+                                               const A* Ah, int, int lda,
+                                               int kb, const Frag (&b)[NTW],
+                                               int ntiles, int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    ring_gemm<NTW, P, NK, bf16x8>(
-        nk, ntiles,
-        [&](int kb, int t) {
-          return gld8(Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) *
-                               8);
-        },
-        [&](int kb, const bf16x8(&b)[NTW]) {
-          bf16x8 ah[MT];
+    bf16x8 ah[MT];
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            ah[mt] = lds8(Ah + (mt * 16 + r) * lda + kb * 32 + kq);
+    for (int mt = 0; mt < MT; ++mt)
+      ah[mt] = lds8(Ah + (mt * 16 + r) * lda + kb * 32 + kq);
 #pragma unroll
-          for (int t = 0; t < NTW; ++t)
-            if (t < ntiles)
+    for (int t = 0; t < NTW; ++t)
+      if (t < ntiles)
 #pragma unroll
-              for (int mt = 0; mt < MT; ++mt)
-                acc[mt][t] = mfma(ah[mt], b[t], acc[mt][t]);
-        });
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][t] = mfma(ah[mt], b[t], acc[mt][t]);
   }
 };
 
@@ -267,52 +276,97 @@ struct Bf1 {
 struct F32 {
   typedef float W;
   typedef float A;
+  typedef f32x8 Frag;
   static constexpr int kPlanes = 1, kPad = 4, kFragRegs = 8;
   __device__ static __forceinline__ void put(A* p, int, int off, float v) {
     p[off] = v;
   }
-  template <int MT, int NTW, int P = ring_depth(NTW, kFragRegs), int NK = 0>
-  __device__ static __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
-                                              const A* Ah, int, int lda,
-                                              const W* Bp, int nk, int nn,
-                                              int nb0, int nstep, int ntiles,
-                                              int lane) {
+  __device__ static __forceinline__ Frag frag(const W* Bp, long f, int lane) {
+    const W* q = Bp + (f * 64 + lane) * 8;
+    return f32x8{*reinterpret_cast<const f32x4*>(q),
+                 *reinterpret_cast<const f32x4*>(q + 4)};
+  }
+  template <int MT, int NTW>
+  __device__ static __forceinline__ void block(f32x4 (&acc)[MT][NTW],
+                                               const A* Ah, int, int lda,
+                                               int kb, const Frag (&b)[NTW],
+                                               int ntiles, int lane) {
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    ring_gemm<NTW, P, NK, f32x8>(
-        nk, ntiles,
-        [&](int kb, int t) {
-          const W* q =
-              Bp + ((size_t)(kb * nn + nb0 + t * nstep) * 64 + lane) * 8;
-          return f32x8{*reinterpret_cast<const f32x4*>(q),
-                       *reinterpret_cast<const f32x4*>(q + 4)};
-        },
-        [&](int kb, const f32x8(&b)[NTW]) {
-          f32x4 a0[MT], a1[MT];
+    f32x4 a0[MT], a1[MT];
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const A* q = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
-            a0[mt] = *reinterpret_cast<const f32x4*>(q);
-            a1[mt] = *reinterpret_cast<const f32x4*>(q + 4);
-          }
+    for (int mt = 0; mt < MT; ++mt) {
+      const A* q = Ah + (mt * 16 + r) * lda + kb * 32 + kq;
+      a0[mt] = *reinterpret_cast<const f32x4*>(q);
+      a1[mt] = *reinterpret_cast<const f32x4*>(q + 4);
+    }
 #pragma unroll
-          for (int t = 0; t < NTW; ++t) {
-            if (t < ntiles) {
+    for (int t = 0; t < NTW; ++t) {
+      if (t < ntiles) {
 #pragma unroll
-              for (int mt = 0; mt < MT; ++mt) {
+        for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                  acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                      a0[mt][q], b[t].lo[q], acc[mt][t], 0, 0, 0);
+          for (int q = 0; q < 4; ++q)
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                a0[mt][q], b[t].lo[q], acc[mt][t], 0, 0, 0);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                  acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                      a1[mt][q], b[t].hi[q], acc[mt][t], 0, 0, 0);
-              }
-            }
-          }
-        });
+          for (int q = 0; q < 4; ++q)
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                a1[mt][q], b[t].hi[q], acc[mt][t], 0, 0, 0);
+        }
+      }
+    }
   }
 };
+
+// A layer product's weight ring: NTW column tiles nb0 + t * nstep of the
+// packed layer at Bp (nn column tiles a k block), P blocks in flight.
+template <class Op, int NTW, int P = ring_depth(NTW, Op::kFragRegs),
+          int NK = 0>
+struct WRing {
+  Ring<typename Op::Frag, NTW, P, NK> r;
+  const typename Op::W* Bp;
+  int nk, nn, nb0, nstep, ntiles, lane;
+  __device__ __forceinline__ typename Op::Frag load(int kb, int t) const {
+    return Op::frag(Bp, (long)kb * nn + nb0 + t * nstep, lane);
+  }
+  __device__ __forceinline__ void start(const typename Op::W* bp, int nk_,
+                                        int nn_, int nb0_, int nstep_,
+                                        int ntiles_, int lane_) {
+    Bp = bp;
+    nk = nk_;
+    nn = nn_;
+    nb0 = nb0_;
+    nstep = nstep_;
+    ntiles = ntiles_;
+    lane = lane_;
+    ring_start<NTW>(r, nk, ntiles, [&](int kb, int t) { return load(kb, t); });
+  }
+  // C[MT][NTW] += A (LDS, Op's layout) x the layer
+  template <int MT>
+  __device__ __forceinline__ void run(f32x4 (&acc)[MT][NTW],
+                                      const typename Op::A* Ah, int plane,
+                                      int lda) {
+    ring_run<NTW>(r, nk, ntiles, [&](int kb, int t) { return load(kb, t); },
+                  [&](int kb, const typename Op::Frag(&b)[NTW]) {
+                    Op::template block<MT, NTW>(acc, Ah, plane, lda, kb, b,
+                                                ntiles, lane);
+                  });
+  }
+};
+
+// C[MT][NTW] += A(LDS at Ah, K = 32 nk) x B(packed layer at Bp, column
+// tiles nb0 + t * nstep, t < ntiles), the weights requested here.
+template <class Op, int MT, int NTW, int P = ring_depth(NTW, Op::kFragRegs),
+          int NK = 0>
+__device__ __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
+                                     const typename Op::A* Ah, int plane,
+                                     int lda, const typename Op::W* Bp, int nk,
+                                     int nn, int nb0, int nstep, int ntiles,
+                                     int lane) {
+  WRing<Op, NTW, P, NK> w;
+  w.start(Bp, nk, nn, nb0, nstep, ntiles, lane);
+  w.template run<MT>(acc, Ah, plane, lda);
+}
 
 // The field for the 16-row tile starting at instance r0 (MLP: 16
 // instances; CNF: 8 instances and their 8 tangent rows), by a workgroup of
@@ -346,6 +400,16 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   __shared__ int any_running;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Weight rings of the three layers.  DEEP: each is requested one phase
+  // ahead (layer 1's at entry, layer 2's after layer 1's products, layer
+  // 3's after layer 2's), so its first blocks arrive during other work.
+  const W* wp = static_cast<const W*>(a.w.packed);
+  const int ntiles3 = (dm.nn3 - wave + WV - 1) / WV;
+  WRing<Op, NTW, DEEP ? (PH < 4 ? PH : 4) : 2> w1;
+  WRing<Op, NTW, PH, NKH> w2;
+  WRing<Op, 4, P4, NKH> w3;
+  if constexpr (DEEP) w1.start(wp, dm.nk1, dm.nn1, wave * NTW, 1, NTW, lane);
+
   if (tid == 0) any_running = 0;
   __syncthreads();
   if (tid < PR && r0 + tid < B && a.status[r0 + tid] == kRunning)
@@ -353,18 +417,44 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   __syncthreads();
   if (!any_running) return;
 
-  // prologue: stage input (FP32) -> split bf16 in LDS; tangent rows = probe
-  for (int idx = tid; idx < PR * D; idx += blockDim.x) {
-    const int r = idx / D, c = idx % D, row = r0 + r;
-    float Yv = 0.f;
-    if (row < B) {
-      float acc = 0.f;
-      for (int j = 0; j < a.n; ++j)
-        acc += a.coef[j] * a.K[((long)a.kidx[j] * B + row) * D + c];
-      Yv = a.y[(long)row * D + c] + a.hs[row] * acc;
-      if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
+  // prologue: stage input (FP32) -> split bf16 in LDS; tangent rows = probe.
+  // Two elements a thread at a time, every load first (at clamped rows):
+  // the stage-input store may alias them as far as the compiler knows, so
+  // loads after it would each wait for the one before.
+  float tv = 0.f;
+  if (tid < PR) {
+    const int row = r0 + tid < B ? r0 + tid : B - 1;
+    tv = float(a.t[row] + a.c * double(a.hs[row]));
+  }
+  for (int i0 = tid; i0 < PR * D; i0 += 2 * (int)blockDim.x) {
+    float kv[2][6], yv[2], hv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = i0 + u * (int)blockDim.x;
+      const int ii = idx < PR * D ? idx : 0;
+      const int c = ii % D, row = r0 + ii / D < B ? r0 + ii / D : B - 1;
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        kv[u][j] = j < a.n ? a.K[((long)a.kidx[j] * B + row) * D + c] : 0.f;
+      yv[u] = a.y[(long)row * D + c];
+      hv[u] = a.hs[row];
     }
-    if (c < din) Op::put(Xh, PX, r * SX + c, Yv);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = i0 + u * (int)blockDim.x;
+      if (idx >= PR * D) continue;
+      const int r = idx / D, c = idx % D, row = r0 + r;
+      float Yv = 0.f;
+      if (row < B) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+          if (j < a.n) acc += a.coef[j] * kv[u][j];
+        Yv = yv[u] + hv[u] * acc;
+        if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
+      }
+      if (c < din) Op::put(Xh, PX, r * SX + c, Yv);
+    }
   }
   for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
     const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
@@ -377,10 +467,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
       Op::put(Xh, PX, (PR + r) * SX + c, e);
     }
   }
-  for (int r = tid; r < PR; r += blockDim.x) {
-    const int row = r0 + r;
-    tcol[r] = row < B ? float(a.t[row] + a.c * double(a.hs[row])) : 0.f;
-  }
+  if (tid < PR) tcol[tid] = r0 + tid < B ? tv : 0.f;
   __syncthreads();
 
   const float* b1 = a.w.fvec;
@@ -390,6 +477,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   const int rq = (lane >> 4) * 4, col = lane & 15;
 
   // hidden layers: wave w owns column tiles w * NTW .. w * NTW + NTW - 1
+#pragma unroll
   for (int layer = 0; layer < 2; ++layer) {
     f32x4 acc[MT][NTW];
 #pragma unroll
@@ -399,8 +487,9 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
     // the layer's bias (and time weight) at this lane's columns, requested
     // ahead of the products: in the epilogue they would be re-read after
     // every store that might alias them
+    constexpr bool kHoist = DEEP || NTW <= 4;
     float bn[NTW], wn[NTW];
-    if constexpr (DEEP) {
+    if constexpr (kHoist) {
       const float* bias = layer == 0 ? b1 : b2;
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
@@ -409,12 +498,19 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
         wn[t] = layer == 0 ? w1t[n] : 0.f;
       }
     }
-    if (layer == 0)
-      Op::template gemm<MT, NTW, PH>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packed), dm.nk1, dm.nn1, wave * NTW, 1,
-                    NTW, lane);
-    else
-      Op::template gemm<MT, NTW, PH, NKH>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off2, dm.nk2, dm.nn2,
-                    wave * NTW, 1, NTW, lane);
+    if (layer == 0) {
+      if constexpr (!DEEP)
+        w1.start(wp, dm.nk1, dm.nn1, wave * NTW, 1, NTW, lane);
+      w1.template run<MT>(acc, Xh, PX, SX);
+      if constexpr (DEEP)
+        w2.start(wp + dm.off2, dm.nk2, dm.nn2, wave * NTW, 1, NTW, lane);
+    } else {
+      if constexpr (!DEEP)
+        w2.start(wp + dm.off2, dm.nk2, dm.nn2, wave * NTW, 1, NTW, lane);
+      w2.template run<MT>(acc, Ah, PA, SA);
+      if (DEEP && ntiles3 > 0)
+        w3.start(wp + dm.off3, dm.nk3, dm.nn3, wave, WV, ntiles3, lane);
+    }
     __syncthreads();  // every wave has read its layer input
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -427,7 +523,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
           float v = acc[mt][t][i];
           const bool primal = !CNF || row < PR;
           if (primal) {
-            if constexpr (DEEP) {
+            if constexpr (kHoist) {
               v += bn[t];
               if (layer == 0) v += tcol[row] * wn[t];
             } else {
@@ -454,7 +550,7 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
 
   // output layer: column tiles nb = wave, wave + WV, ...
   {
-    const int ntiles = (dm.nn3 - wave + WV - 1) / WV;
+    const int ntiles = ntiles3;
     f32x4 acc[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -477,9 +573,11 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
                              : 0.f;
         }
     }
-    if (ntiles > 0)
-      Op::template gemm<MT, 4, P4, NKH>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packed) + dm.off3, dm.nk3, dm.nn3, wave,
-                  WV, ntiles, lane);
+    if (ntiles > 0) {
+      if constexpr (!DEEP)
+        w3.start(wp + dm.off3, dm.nk3, dm.nn3, wave, WV, ntiles, lane);
+      w3.template run<MT>(acc, Ah, PA, SA);
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
