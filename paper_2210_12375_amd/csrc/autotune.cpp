@@ -81,7 +81,8 @@ int autotune(const bode_config* cfg, const bode_problem* p, void* workspace,
     const bool fused = mfma && !cfg->keep_dense;
     std::vector<int> waves = {0};
     if (mfma && cfg->mlp_hidden > 64) {
-      const int def = mfma_waves(cfg->mlp_hidden, cfg->rhs == BODE_RHS_CNF, 0);
+      const int def = mfma_waves(cfg->mlp_hidden, cfg->rhs == BODE_RHS_CNF,
+                                 cfg->B, 0);
       waves = {def, def == 8 ? 4 : 8};
     }
     std::vector<int> rounds = {0};

@@ -532,7 +532,7 @@ hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
 // instances), while its VJP is faster on 8.
 template <class Op, bool CNF>
 hipError_t field_h(const MfmaArgs& a, hipStream_t s) {
-  const int wv = mfma_waves(a.H, CNF, a.waves);
+  const int wv = mfma_waves(a.H, CNF, a.B, a.waves);
   switch (a.H) {
     case 512:
       return wv == 4 ? launch_t<Op, 8, CNF, 4>(a, s)
@@ -570,13 +570,19 @@ size_t mfma_packedT_bytes(int din, int H, int f32) {
 
 size_t mfma_fvec_elems(int din, int H) { return 3 * (size_t)H + din; }
 
-int mfma_waves(int H, bool cnf, int requested) {
+int mfma_waves(int H, bool cnf, int B, int requested) {
   if (H <= 64) return 4;  // one 16-column tile per wavefront at most
   if (requested == 4 || requested == 8) return requested;
-  // measured defaults: 8 wavefronts (two per SIMD) from width 128 up,
-  // except the CNF at width 512 (its tangent rows double the epilogue
-  // registers; 62 vs 75 us per stage evaluation of 8192 instances on 4)
-  return (cnf && H == 512) ? 4 : 8;
+  // measured defaults: 8 wavefronts (two per SIMD) from width 128 up while
+  // the tiles are about one per compute unit; 4 once there are two or more
+  // tiles per compute unit, so that two workgroups share one (MLP at width
+  // 256, fused solve: 16,384 instances 1.45 -> 1.15 ms, 65,536 5.13 -> 3.98
+  // ms, 4096 0.45 vs 0.51 ms on 4); and 4 for the CNF at width 512 (its
+  // tangent rows double the epilogue registers; 62 vs 75 us per stage
+  // evaluation of 8192 instances)
+  if (cnf && H == 512) return 4;
+  const long tiles = (B + (cnf ? 7 : 15)) / (cnf ? 8 : 16);
+  return H >= 256 && tiles >= 512 ? 4 : 8;
 }
 
 std::string mfma_supported(int din, int H) {

@@ -30,7 +30,7 @@ size_t mfma_fvec_elems(int din, int H);
 std::string mfma_supported(int din, int H);
 // Wavefronts per 16-row tile the field kernels use: `requested` (4 or 8)
 // where the width allows it, else the default for the shape.
-int mfma_waves(int H, bool cnf, int requested);
+int mfma_waves(int H, bool cnf, int B, int requested);
 
 hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
                              const float* W1, const float* b1, const float* W2,

@@ -755,7 +755,7 @@ hipError_t fused_t(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
 // H = 512: 2.89 vs 3.35 ms per solve of 8192 instances).
 template <class Op, bool CNF, class M>
 hipError_t fused_h(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
-  const int wv = mfma_waves(m.H, CNF, f.st[0].waves);
+  const int wv = mfma_waves(m.H, CNF, m.B, f.st[0].waves);
   switch (m.H) {
     case 512:
       return wv == 4 ? fused_t<Op, 8, CNF, 4, M>(m, f, s)
@@ -1948,10 +1948,16 @@ hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int nb = 1, long sin = 0, long sg = 0,
                             long sslot = 0) {
   if (nb < 1 || (nb > 1 && sslot < (long)S * P)) return hipErrorInvalidValue;
-  // tile shape: narrow where the layer has few inputs or outputs
+  // tile shape (FP32 matrix cores: 32 WM x 32 WN): narrow where the layer
+  // has few inputs or outputs, so little of a tile is padding (a 257 x 64
+  // layer on 128 x 64 tiles, 66 x 256 on 96 x 128)
   const bool f32 = std::is_same<R, float>::value;
-  const int tm = !f32 ? 64 : (M <= 32 ? 32 : 128);
-  const int tn = !f32 ? 64 : (N <= 32 && M > 32 ? 32 : 128);
+  int wm = 4, wn = 4;
+  if (M <= 32) wm = 1;
+  else if (N <= 32) wn = 1;
+  else if (N <= 64 && M > 64) wn = 2;
+  else if (M <= 96 && N > 64) wm = 3;
+  const int tm = !f32 ? 64 : 32 * wm, tn = !f32 ? 64 : 32 * wn;
   const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
   // k-splits: a few rounds of workgroups over the chip (about 2048 over
   // all nb products, so the last round's tail is short), each split at
@@ -1975,11 +1981,17 @@ hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                          sslot);
       return hipGetLastError();
     }
-    if (tm == 32)
+    if (wm == 1)
       hipLaunchKernelGGL((grad_gemm_mfma<1, 4>), g, blk, 0, s, Tin, Tg, K, M,
                          N, splits, slots, P, off, sin, sg, sslot);
-    else if (tn == 32)
+    else if (wn == 1)
       hipLaunchKernelGGL((grad_gemm_mfma<4, 1>), g, blk, 0, s, Tin, Tg, K, M,
+                         N, splits, slots, P, off, sin, sg, sslot);
+    else if (wn == 2)
+      hipLaunchKernelGGL((grad_gemm_mfma<4, 2>), g, blk, 0, s, Tin, Tg, K, M,
+                         N, splits, slots, P, off, sin, sg, sslot);
+    else if (wm == 3)
+      hipLaunchKernelGGL((grad_gemm_mfma<3, 4>), g, blk, 0, s, Tin, Tg, K, M,
                          N, splits, slots, P, off, sin, sg, sslot);
     else
       hipLaunchKernelGGL((grad_gemm_mfma<4, 4>), g, blk, 0, s, Tin, Tg, K, M,
