@@ -57,13 +57,30 @@ __global__ __launch_bounds__(64 * WV) void field_mfma_kernel(MfmaArgs a) {
   field_tile<Op, NTW, CNF, WV>(a, blockIdx.x * (CNF ? 8 : 16), smem_raw);
 }
 
+// Several stage evaluations of one step in one launch, in order: a tile's
+// stage inputs depend only on its own rows' earlier stages, which pass
+// between the tile's waves through memory (the barrier orders them).
 template <class Op, int NTW, bool CNF, int WV>
-hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
+__global__ __launch_bounds__(64 * WV) void field_steps_kernel(MfmaSteps v) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  for (int i = 0; i < v.n; ++i) {
+    field_tile<Op, NTW, CNF, WV>(v.st[i], blockIdx.x * (CNF ? 8 : 16),
+                                 smem_raw);
+    __syncthreads();
+  }
+}
+
+template <class Op, int NTW, bool CNF, int WV>
+hipError_t launch_t(const MfmaArgs& a, const MfmaSteps* v, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
   const size_t sm = mfma_smem<Op, NTW, CNF, WV>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((field_mfma_kernel<Op, NTW, CNF, WV>),
-                     dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
+  if (v != nullptr)
+    hipLaunchKernelGGL((field_steps_kernel<Op, NTW, CNF, WV>),
+                       dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, *v);
+  else
+    hipLaunchKernelGGL((field_mfma_kernel<Op, NTW, CNF, WV>),
+                       dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
   return hipGetLastError();
 }
 
@@ -81,8 +98,8 @@ hipError_t launch_t(const MfmaArgs& a, hipStream_t s) {
 // workgroup hides more of the three-layer dependent chain (measured 156 ->
 // 133 us per stage for 8192 instances).
 template <class Op, int NTW, bool CNF, int WV>
-__global__ __launch_bounds__(64 * WV) __attribute__((
-    amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_mfma_kernel(MfmaVjpArgs a) {
+__device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
+                                         unsigned char* smem_raw) {
   typedef typename Op::A A;
   typedef typename Op::W W;
   constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 16 * WV,
@@ -95,7 +112,6 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
   const Dims dm = dims(din, H);
   const DimsT dt = dims_t(din, H);
   const int SX = dm.K1 + Op::kPad;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int PX = RT * SX, PA = RT * SA;
   A* Xh = reinterpret_cast<A*>(smem_raw);
   A* Ah = Xh + Op::kPlanes * PX;
@@ -106,6 +122,17 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = blockIdx.x * PR;
+  // Weight rings of the transposed layers.  With the stored forward layers
+  // (and outside the register-bound CNF kernel) each is requested one
+  // phase ahead: W3^T's at entry, W2^T's after S2's products, W1^T's after
+  // S1's.
+  const W* wt = static_cast<const W*>(a.w.packedT);
+  const bool ahead = !CNF && a.act_in != nullptr;
+  const int ntiles1 = (dt.nn1 - wave + WV - 1) / WV;
+  WRing<Op, NTW, PD> r3;
+  WRing<Op, NTW, PD, H / 32> r2;
+  WRing<Op, 4, PD4, H / 32> r1;
+  if (ahead) r3.start(wt, dt.nk3, dt.nn3, wave * NTW, 1, NTW, lane);
   if (tid == 0) any_running = 0;
   __syncthreads();
   if (tid < PR) {
@@ -387,12 +414,15 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
     f32x4 acc[1][NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (layer == 1)
-      gemm<Op, 1, NTW, PD>(acc, Xh, PX, SX, static_cast<const W*>(a.w.packedT), dt.nk3, dt.nn3, wave * NTW, 1,
-                   NTW, lane);
-    else
-      gemm<Op, 1, NTW, PD, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off2, dt.nk2, dt.nn2,
-                   wave * NTW, 1, NTW, lane);
+    if (layer == 1) {
+      if (!ahead) r3.start(wt, dt.nk3, dt.nn3, wave * NTW, 1, NTW, lane);
+      r3.template run<1>(acc, Xh, PX, SX);
+      r2.start(wt + dt.off2, dt.nk2, dt.nn2, wave * NTW, 1, NTW, lane);
+    } else {
+      r2.template run<1>(acc, Ah, PA, SA);
+      if (ahead && ntiles1 > 0)
+        r1.start(wt + dt.off1, dt.nk1, dt.nn1, wave, WV, ntiles1, lane);
+    }
     __syncthreads();
     float* Tg = layer == 1 ? a.T2g : a.T1g;
 #pragma unroll
@@ -423,13 +453,15 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 
   // mu = G1 W1^T (primal rows); column tiles nb = wave, wave + WV, ...
   {
-    const int ntiles = (dt.nn1 - wave + WV - 1) / WV;
+    const int ntiles = ntiles1;
     f32x4 acc[1][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[0][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (ntiles > 0)
-      gemm<Op, 1, 4, PD4, H / 32>(acc, Ah, PA, SA, static_cast<const W*>(a.w.packedT) + dt.off1, dt.nk1, dt.nn1, wave,
-                 WV, ntiles, lane);
+    if (ntiles > 0) {
+      if (!ahead)
+        r1.start(wt + dt.off1, dt.nk1, dt.nn1, wave, WV, ntiles, lane);
+      r1.template run<1>(acc, Ah, PA, SA);
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t >= ntiles) continue;
@@ -491,12 +523,38 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 }
 
 template <class Op, int NTW, bool CNF, int WV>
-hipError_t launch_vjp_t(const MfmaVjpArgs& a, hipStream_t s) {
+__global__ __launch_bounds__(64 * WV) __attribute__((
+    amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_mfma_kernel(MfmaVjpArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  vjp_tile<Op, NTW, CNF, WV>(a, smem_raw);
+}
+
+// The stages of one step in one launch (stage 7 first): a tile's rows
+// depend on no other tile's, so its workgroup runs the stages in turn, the
+// cotangents passing between them through memory (the barrier orders them;
+// all of the tile's waves share the compute unit's cache).
+template <class Op, int NTW, bool CNF, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((
+    amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_steps_kernel(MfmaVjpSteps v) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  for (int i = 0; i < v.n; ++i) {
+    vjp_tile<Op, NTW, CNF, WV>(v.st[i], smem_raw);
+    __syncthreads();
+  }
+}
+
+template <class Op, int NTW, bool CNF, int WV>
+hipError_t launch_vjp_t(const MfmaVjpArgs& a, const MfmaVjpSteps* v,
+                        hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
   const size_t sm = mfma_smem<Op, NTW, CNF, WV>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF, WV>),
-                     dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
+  if (v != nullptr)
+    hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV>),
+                       dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, *v);
+  else
+    hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF, WV>),
+                       dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
   return hipGetLastError();
 }
 
@@ -531,29 +589,29 @@ hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
 // for its 8 primal + 8 tangent rows (62 vs 75 us per stage at 8192
 // instances), while its VJP is faster on 8.
 template <class Op, bool CNF>
-hipError_t field_h(const MfmaArgs& a, hipStream_t s) {
+hipError_t field_h(const MfmaArgs& a, const MfmaSteps* v, hipStream_t s) {
   const int wv = mfma_waves(a.H, CNF, a.B, a.waves);
   switch (a.H) {
     case 512:
-      return wv == 4 ? launch_t<Op, 8, CNF, 4>(a, s)
-                     : launch_t<Op, 4, CNF, 8>(a, s);
+      return wv == 4 ? launch_t<Op, 8, CNF, 4>(a, v, s)
+                     : launch_t<Op, 4, CNF, 8>(a, v, s);
     case 256:
-      return wv == 4 ? launch_t<Op, 4, CNF, 4>(a, s)
-                     : launch_t<Op, 2, CNF, 8>(a, s);
+      return wv == 4 ? launch_t<Op, 4, CNF, 4>(a, v, s)
+                     : launch_t<Op, 2, CNF, 8>(a, v, s);
     case 128:
-      return wv == 4 ? launch_t<Op, 2, CNF, 4>(a, s)
-                     : launch_t<Op, 1, CNF, 8>(a, s);
-    default: return launch_t<Op, 1, CNF, 4>(a, s);
+      return wv == 4 ? launch_t<Op, 2, CNF, 4>(a, v, s)
+                     : launch_t<Op, 1, CNF, 8>(a, v, s);
+    default: return launch_t<Op, 1, CNF, 4>(a, v, s);
   }
 }
 
 template <class Op, bool CNF>
-hipError_t vjp_h(const MfmaVjpArgs& a, hipStream_t s) {
+hipError_t vjp_h(const MfmaVjpArgs& a, const MfmaVjpSteps* v, hipStream_t s) {
   switch (a.H) {
-    case 512: return launch_vjp_t<Op, 4, CNF, 8>(a, s);
-    case 256: return launch_vjp_t<Op, 2, CNF, 8>(a, s);
-    case 128: return launch_vjp_t<Op, 1, CNF, 8>(a, s);
-    default: return launch_vjp_t<Op, 1, CNF, 4>(a, s);
+    case 512: return launch_vjp_t<Op, 4, CNF, 8>(a, v, s);
+    case 256: return launch_vjp_t<Op, 2, CNF, 8>(a, v, s);
+    case 128: return launch_vjp_t<Op, 1, CNF, 8>(a, v, s);
+    default: return launch_vjp_t<Op, 1, CNF, 4>(a, v, s);
   }
 }
 
@@ -626,20 +684,40 @@ MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,
   return a;
 }
 
-hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s) {
+static hipError_t vjp_any(const MfmaVjpArgs& a, const MfmaVjpSteps* v,
+                          hipStream_t s) {
   if (a.w.packedT == nullptr || a.w.plain) return hipErrorInvalidValue;
   if (a.w.f32)
-    return a.cnf ? vjp_h<F32, true>(a, s) : vjp_h<F32, false>(a, s);
-  return a.cnf ? vjp_h<Bf3, true>(a, s) : vjp_h<Bf3, false>(a, s);
+    return a.cnf ? vjp_h<F32, true>(a, v, s) : vjp_h<F32, false>(a, v, s);
+  return a.cnf ? vjp_h<Bf3, true>(a, v, s) : vjp_h<Bf3, false>(a, v, s);
+}
+
+hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s) {
+  return vjp_any(a, nullptr, s);
+}
+
+hipError_t launch_vjp_steps_mfma(const MfmaVjpSteps& v, hipStream_t s) {
+  if (v.n < 1 || v.n > 7) return hipErrorInvalidValue;
+  return vjp_any(v.st[0], &v, s);
+}
+
+static hipError_t field_any(const MfmaArgs& a, const MfmaSteps* v,
+                            hipStream_t s) {
+  if (a.w.f32)
+    return a.cnf ? field_h<F32, true>(a, v, s) : field_h<F32, false>(a, v, s);
+  if (a.w.plain)
+    return a.cnf ? field_h<Bf1, true>(a, v, s) : field_h<Bf1, false>(a, v, s);
+  return a.cnf ? field_h<Bf3, true>(a, v, s) : field_h<Bf3, false>(a, v, s);
 }
 
 hipError_t launch_field_mfma(const MfmaArgs& a, int row_tile, hipStream_t s) {
   (void)row_tile;
-  if (a.w.f32)
-    return a.cnf ? field_h<F32, true>(a, s) : field_h<F32, false>(a, s);
-  if (a.w.plain)
-    return a.cnf ? field_h<Bf1, true>(a, s) : field_h<Bf1, false>(a, s);
-  return a.cnf ? field_h<Bf3, true>(a, s) : field_h<Bf3, false>(a, s);
+  return field_any(a, nullptr, s);
+}
+
+hipError_t launch_field_steps_mfma(const MfmaSteps& v, hipStream_t s) {
+  if (v.n < 1 || v.n > 7) return hipErrorInvalidValue;
+  return field_any(v.st[0], &v, s);
 }
 
 }  // namespace bode

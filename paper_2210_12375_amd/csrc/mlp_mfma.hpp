@@ -102,4 +102,21 @@ struct MfmaVjpArgs {
 
 hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s);
 
+// Up to seven stages of one step, each with its own arguments, in one
+// launch, in the order given (same shape and weights in every entry).
+struct MfmaVjpSteps {
+  MfmaVjpArgs st[7];
+  int n;
+};
+hipError_t launch_vjp_steps_mfma(const MfmaVjpSteps& v, hipStream_t s);
+
+struct MfmaSteps {
+  MfmaArgs st[7];
+  int n;
+};
+hipError_t launch_field_steps_mfma(const MfmaSteps& v, hipStream_t s);
+// both travel as kernel arguments
+static_assert(sizeof(MfmaVjpSteps) <= 4096 && sizeof(MfmaSteps) <= 4096,
+              "step arguments exceed the kernel-argument space");
+
 }  // namespace bode

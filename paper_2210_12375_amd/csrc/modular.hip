@@ -1369,13 +1369,21 @@ __global__ void adj_load_ckpt(Mod<R> m, Back<R> b, int seg, R* dst) {
                              : m.y0[i];
 }
 
-// Cotangents injected by the dense outputs of step n.
+// Cotangents injected by the dense outputs of step n; with setup, also
+// the step view of step n (adj_setup without the state copy).
 template <typename R, class M>
-__global__ void adj_dense(Mod<R> m, Back<R> b, int n, const R* g_eval) {
+__global__ void adj_dense(Mod<R> m, Back<R> b, int n, const R* g_eval,
+                          int setup) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (row >= m.B) return;
   const int D = m.D, B = m.B;
+  if (setup && lane == 0) {
+    const bool on = n < b.nacc[row];
+    b.act[row] = on ? kRunning : kSuccess;
+    b.bh[row] = on ? R(b.hacc[(long)row * b.cap + n]) : R(0);
+    b.bt[row] = on ? b.tn[(long)row * (b.cap + 1) + n] : 0.0;
+  }
   for (int c = lane; c < D; c += 64) {
     b.lamn[(long)row * D + c] = R(0);
     for (int j = 0; j < 7; ++j) b.kap[((long)j * B + row) * D + c] = R(0);
@@ -1629,6 +1637,46 @@ hipError_t launch_vjp(const Mod<R>& m, const Back<R>& b, const VjpSpec& sp,
   return hipGetLastError();
 }
 
+// The matrix-core VJP kernel's arguments for stage sp.s of the step.
+MfmaVjpArgs vjp_args(const ModImpl& im, const Mod<float>& m,
+                     const Back<float>& b, const VjpSpec& sp) {
+  MfmaVjpArgs a{};
+  a.B = m.B;
+  a.D = m.D;
+  a.din = m.d_in;
+  a.H = m.H;
+  a.cnf = m.cnf;
+  a.act = b.act;
+  a.Y = sp.Y != nullptr ? static_cast<const float*>(sp.Y)
+                        : b.Ys + (long)(sp.s - 1) * m.B * m.D;
+  a.act_in = sp.act_in;
+  a.kap_s = b.kap + (long)(sp.s - 1) * m.B * m.D;
+  a.eps = m.eps;
+  a.bh = b.bh;
+  a.bt = b.bt;
+  a.c = sp.c;
+  a.w = im.mw;
+  a.T1in = b.T1in;
+  a.T1g = b.T1g;
+  a.T2in = b.T2in;
+  a.T2g = b.T2g;
+  a.T3in = b.T3in;
+  a.T3g = b.T3g;
+  a.K = b.K;
+  a.kb = sp.kbase + (long)(sp.s - 1) * (m.cnf ? 2L * m.B : (long)m.B);
+  a.s = sp.s;
+  a.n = sp.n;
+  for (int j = 0; j < sp.n; ++j) {
+    a.kidx[j] = sp.kidx[j];
+    a.coef[j] = float(sp.coef[j]);
+  }
+  a.lam = b.lam;
+  a.lamn = b.lamn;
+  a.kap = b.kap;
+  a.mu_out = static_cast<float*>(sp.mu_out);
+  return a;
+}
+
 // Matrix-core modes: the stage's VJP on MFMA (BF16: BF16 weights, three-way
 // split activations and cotangents; FP32: FP32 operands; both accumulate in
 // FP32); else the FMA kernel.
@@ -1636,46 +1684,12 @@ template <typename R>
 hipError_t vjp(const ModImpl& im, const Mod<R>& m, const Back<R>& b,
                const VjpSpec& sp, hipStream_t s) {
   if constexpr (std::is_same<R, float>::value) {
-    if (im.mw.packedT != nullptr) {
-      MfmaVjpArgs a{};
-      a.B = m.B;
-      a.D = m.D;
-      a.din = m.d_in;
-      a.H = m.H;
-      a.cnf = m.cnf;
-      a.act = b.act;
-      a.Y = sp.Y != nullptr ? static_cast<const float*>(sp.Y)
-                            : b.Ys + (long)(sp.s - 1) * m.B * m.D;
-      a.act_in = sp.act_in;
-      a.kap_s = b.kap + (long)(sp.s - 1) * m.B * m.D;
-      a.eps = m.eps;
-      a.bh = b.bh;
-      a.bt = b.bt;
-      a.c = sp.c;
-      a.w = im.mw;
-      a.T1in = b.T1in;
-      a.T1g = b.T1g;
-      a.T2in = b.T2in;
-      a.T2g = b.T2g;
-      a.T3in = b.T3in;
-      a.T3g = b.T3g;
-      a.K = b.K;
-      a.kb = sp.kbase + (long)(sp.s - 1) * (m.cnf ? 2L * m.B : (long)m.B);
-      a.s = sp.s;
-      a.n = sp.n;
-      for (int j = 0; j < sp.n; ++j) {
-        a.kidx[j] = sp.kidx[j];
-        a.coef[j] = float(sp.coef[j]);
-      }
-      a.lam = b.lam;
-      a.lamn = b.lamn;
-      a.kap = b.kap;
-      a.mu_out = static_cast<float*>(sp.mu_out);
-      return launch_vjp_mfma(a, s);
-    }
+    if (im.mw.packedT != nullptr)
+      return launch_vjp_mfma(vjp_args(im, m, b, sp), s);
   }
   return launch_vjp<R>(m, b, sp, s);
 }
+
 
 template <typename R>
 __global__ void fill_r(R* p, long n, R v) {
@@ -2036,6 +2050,12 @@ namespace {
 
 inline dim3 lin_grid(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// At most two 16-row tiles (CNF: 8 instances) per compute unit.
+template <typename R>
+bool few_tiles(const Mod<R>& m) {
+  return (m.B + (m.cnf ? 7 : 15)) / (m.cnf ? 8 : 16) <= 512;
+}
+
 template <typename R, class M>
 hipError_t stages(ModImpl& im, Mod<R> v, Back<R>& b, R* y7dst, bool keep_y,
                   hipStream_t s) {
@@ -2062,11 +2082,21 @@ hipError_t stages_store(ModImpl& im, Mod<R> v, Back<R>& b, int j,
   const size_t BD = (size_t)v.B * v.D;
   const size_t AH = (size_t)v.B * (v.cnf ? 2 : 1) * 2 * v.H;
   hipError_t e = hipSuccess;
+  [[maybe_unused]] MfmaSteps fs{};
   for (int st = 0; st < 7 && e == hipSuccess; ++st) {
     StageSpec sp = st == 0 ? StageSpec{} : stage_spec<M>(st);
     sp.yout = st == 0 ? nullptr : b.Yst + ((size_t)j * 7 + st) * BD;
     sp.act_out = b.Ast + ((size_t)j * 7 + st) * AH;
+    if constexpr (std::is_same<R, float>::value) {
+      if (im.mw.packed != nullptr && few_tiles(v)) {  // the seven in one
+        fs.st[fs.n++] = stage_args(im, v, sp, b.Ks + (size_t)st * BD);
+        continue;
+      }
+    }
     e = field<R>(im, v, sp, b.Ks + (size_t)st * BD, s);
+  }
+  if constexpr (std::is_same<R, float>::value) {
+    if (e == hipSuccess && fs.n > 0) e = launch_field_steps_mfma(fs, s);
   }
   return e;
 }
@@ -2106,9 +2136,10 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   // Step n's cotangent chain: dense-output cotangents, the seven stage
   // VJPs (on the stored stage inputs Yh and layers Ah of segment step j,
   // or recomputing), and the chunk's parameter-gradient GEMMs.
-  auto back_step = [&](int n, const R* Yh, const float* Ah,
-                       int j) -> hipError_t {
-    hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval);
+  auto back_step = [&](int n, const R* Yh, const float* Ah, int j,
+                       int setup) -> hipError_t {
+    hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval,
+                       setup);
     // this step's place in its tape chunk (steps are taken in reverse)
     const int slot = (nmax - 1 - n) % b.C;
     const long Bs = m.cnf ? 2L * m.B : (long)m.B;
@@ -2124,6 +2155,13 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       hipLaunchKernelGGL(fill_r<R>, lin_grid((long)m.d_in * rows), blk, 0, s,
                          b.T3g + kbase * m.d_in, (long)m.d_in * rows, R(0));
     }
+    // the seven stages in one launch on the matrix cores while the batch
+    // has few tiles (launches, not the tiles' work, set its pace), else one
+    // launch each (a CNF step of 8192 instances: 16.9 ms one each, 18.9 in
+    // one)
+    [[maybe_unused]] MfmaVjpSteps vs{};
+    const bool steps = std::is_same<R, float>::value && im.mw.packedT &&
+                       few_tiles(m);
     for (int st = 7; st >= 1; --st) {
       VjpSpec sp{};
       sp.s = st;
@@ -2141,7 +2179,17 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
         sp.kidx[q] = ss.kidx[q];
         sp.coef[q] = ss.coef[q];
       }
+      if constexpr (std::is_same<R, float>::value) {
+        if (steps) {
+          vs.st[vs.n++] = vjp_args(im, m, b, sp);
+          continue;
+        }
+      }
       const hipError_t r = vjp<R>(im, m, b, sp, s);
+      if (r != hipSuccess) return r;
+    }
+    if (steps) {
+      const hipError_t r = launch_vjp_steps_mfma(vs, s);
       if (r != hipSuccess) return r;
     }
     if (slot == b.C - 1 || n == 0) {
@@ -2221,11 +2269,8 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       if (e == hipSuccess) e = hipStreamWaitEvent(s, ready[q & 1], 0);
       const R* Yh = b.Yst + (q & 1) * b.yst_half;
       const float* Ah = b.Ast + (q & 1) * b.ast_half;
-      for (int n = seg_top(q); n >= q * k && e == hipSuccess; --n) {
-        hipLaunchKernelGGL(adj_setup<R>, rows_g, blk, 0, s, m, b, n,
-                           (const R*)nullptr, (R*)nullptr);
-        e = back_step(n, Yh, Ah, n - q * k);
-      }
+      for (int n = seg_top(q); n >= q * k && e == hipSuccess; --n)
+        e = back_step(n, Yh, Ah, n - q * k, 1);
       if (e == hipSuccess) e = hipEventRecord(freed[q & 1], s);
     }
     if (e == hipSuccess) e = hipEventRecord(im.ev[5], s2);
@@ -2253,7 +2298,7 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
                          (const R*)yn, b.Ys);
       v.st.y = yn;
       e = stages<R, M>(im, v, b, nullptr, true, s);
-      if (e == hipSuccess) e = back_step(n, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = back_step(n, nullptr, nullptr, 0, 0);
       if (e != hipSuccess) return e;
     }
   }
