@@ -45,7 +45,8 @@ def parse():
                     help="skip the neural-field workloads")
     ap.add_argument("--study", default="",
                     choices=["", "cadjoint", "neural", "ceilings", "hbm",
-                             "paper", "fwdbwd", "fig1", "sweep"],
+                             "paper", "fwdbwd", "fig1", "sweep",
+                             "accuracy"],
                     help="only run one side study and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), "
@@ -436,6 +437,54 @@ def neural_suite(bd, W, rl, steps, warmup, only=None):
     return out
 
 
+def vdp64_rate(bd, W):
+    """The 64-instance Van der Pol batch (FP64 Dormand-Prince, rtol 1e-6,
+    atol 1e-8, 8 evaluation times): accepted instance-steps/s of whole
+    solves (init + solve), median of 20 after 3 warm-ups."""
+    p = W.vdp_batch()
+    dp = bd.device_problem(p, "fp64")
+    wall, solve_ms, st, _, _, _ = timed_solves(bd, dp, "dopri5", "fp64", 20,
+                                               3)
+    acc = int(st["n_accepted"].sum())
+    return {"instances": int(p["y0"].shape[0]), "ms_per_solve": wall,
+            "solve_kernel_ms": float(np.median(solve_ms)), "accepted": acc,
+            "instance_steps_per_s": acc / (wall * 1e-3),
+            "steps_p50": float(np.median(st["n_accepted"])),
+            "steps_max": int(st["n_accepted"].max()),
+            "ok": bool(np.all(st["status"] == 1))}
+
+
+def neural_accuracy(bd, W, n=256):
+    """The neural forward workload's error at its stated tolerance (rtol
+    1e-5, atol 1e-6) on its first n instances, per precision: max over the
+    final state's components of |y - ref| / (rtol |ref| + atol) against the
+    FP64 field solved at rtol 1e-11, atol 1e-13 (median and maximum over
+    instances)."""
+    p = W.subset(W.neural_ode(), np.arange(n))
+    q = W.subset(p, np.arange(n))
+    q["rtol"][:] = 1e-11
+    q["atol"][:] = 1e-13
+    s = bd.Solver(bd.device_problem(q, "fp64"), method="dopri5",
+                  precision="fp64", rhs=bd.RHS_MLP).solve()
+    ref = s.y_final.cpu().numpy()
+    s.close()
+    out = {}
+    for name, prec, kw in (("fp64", "fp64", {}), ("fp32", "fp32", {}),
+                           ("bf16", "bf16", {}),
+                           ("bf16_plain", "bf16", {"plain_bf16": 1})):
+        s = bd.Solver(bd.device_problem(p, prec), method="dopri5",
+                      precision=prec, rhs=bd.RHS_MLP, **kw).solve()
+        y = s.y_final.cpu().numpy().astype(np.float64)
+        na = s.stats()["n_accepted"].cpu().numpy()
+        s.close()
+        tol = p["rtol"][:, None] * np.abs(ref) + p["atol"][:, None]
+        e = (np.abs(y - ref) / tol).max(axis=1)
+        out[name] = {"err_in_tol_units_median": float(np.median(e)),
+                     "err_in_tol_units_max": float(e.max()),
+                     "accepted_steps_p50": float(np.median(na))}
+    return out
+
+
 def cadjoint_study(bd, W, reps=2):
     """Appendix A's adjoint-equation backward: the continuous adjoint solved
     per instance (b (f + p) variables) and jointly (b f + p), beside the
@@ -712,6 +761,11 @@ def main():
     if a.study == "fig1":
         print(json.dumps({"fig1_traces": fig1_traces(bd, W)}), flush=True)
         return
+    if a.study == "accuracy":
+        print(json.dumps({"vdp64_fp64": vdp64_rate(bd, W),
+                          "neural_accuracy": neural_accuracy(bd, W)}),
+              flush=True)
+        return
     if a.study == "fwdbwd":
         print(json.dumps({"neural": neural_suite(bd, W, rl, a.steps, a.warmup,
                                                  only="fwdbwd")}), flush=True)
@@ -829,9 +883,11 @@ def main():
                                     "launch_shape")}
                      for (m, pr), r in results.items()},
     }
+    line["vdp64_fp64"] = vdp64_rate(bd, W)
     if not a.no_neural:
         line["neural"] = neural_suite(bd, W, rl, max(2, a.steps // 4),
                                       min(a.warmup, 2))
+        line["neural_accuracy"] = neural_accuracy(bd, W)
         line["cadjoint_study"] = cadjoint_study(bd, W)
     line["ceilings"] = ceilings()
     line["paper_loop_study"] = paper_loop_study(bd, W)

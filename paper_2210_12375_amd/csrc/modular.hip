@@ -21,8 +21,10 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
+#include <vector>
 
 #include "analytic.hpp"
 #include "common.hpp"
@@ -817,9 +819,8 @@ struct ModImpl {
   // private stream for captures (the caller's may be the null stream,
   // which cannot be captured; graphs are replayed on the caller's)
   hipStream_t cap_stream = nullptr;
-  // the discrete adjoint's second stream (segment recomputation) and its
-  // events: start, ready[2], free[2], done
-  hipStream_t aux_stream = nullptr;
+  // the discrete adjoint's events for its second stream (segment
+  // recomputation): start, ready[2], free[2], done
   hipEvent_t ev[6] = {};
 };
 
@@ -1230,14 +1231,39 @@ size_t modular_layout(const bode_config& c, void* base, ModularPlan* mp) {
   return n;
 }
 
+// Pinned host words for the running-count read-backs, two per handle, kept
+// in a process-wide free list (pinned allocations are slow; handles come
+// and go every training step).
+namespace {
+std::mutex g_pin_mu;
+std::vector<int32_t*> g_pin_free;
+
+hipError_t pinned_take(int32_t** out) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin_free.empty()) {
+      *out = g_pin_free.back();
+      g_pin_free.pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipHostMalloc(reinterpret_cast<void**>(out), 64,
+                       hipHostMallocDefault);
+}
+
+void pinned_give(int32_t* p) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(p);
+}
+}  // namespace
+
 hipError_t modular_init(ModularPlan& mp, const bode_config& c,
                         const bode_problem& p, hipStream_t s) {
   ModImpl* im = static_cast<ModImpl*>(mp.impl);
   if (!im) return hipErrorInvalidValue;
   im->cfg = c;
   im->p = p;
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&im->host_running),
-                               2 * sizeof(int32_t), hipHostMallocDefault);
+  hipError_t e = pinned_take(&im->host_running);
   if (e != hipSuccess) return e;
   auto publish = [&](auto& m) {
     mp.t = m.st.t;
@@ -2216,14 +2242,15 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
     // store half (q - 1) & 1) while the caller's stream runs segment q's
     // cotangent chain on half q & 1.  Both chains are sequences of short
     // launches on a fraction of the compute units, so they overlap.
-    if (im.aux_stream == nullptr) {
-      e = hipStreamCreateWithFlags(&im.aux_stream, hipStreamNonBlocking);
+    if (im.ev[0] == nullptr) {
       for (hipEvent_t& ev : im.ev)
         if (e == hipSuccess && ev == nullptr)
           e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
       if (e != hipSuccess) return e;
     }
-    hipStream_t s2 = im.aux_stream;
+    hipStream_t s2 = nullptr;
+    e = shared_aux_stream(&s2);
+    if (e != hipSuccess) return e;
     hipEvent_t *ready = im.ev + 1, *freed = im.ev + 3;
     e = hipEventRecord(im.ev[0], s);
     if (e == hipSuccess) e = hipStreamWaitEvent(s2, im.ev[0], 0);
@@ -2404,10 +2431,9 @@ hipError_t modular_eval(ModularPlan& mp, const double* t_query, void* y_out,
 void modular_release(ModularPlan& mp) {
   ModImpl* im = static_cast<ModImpl*>(mp.impl);
   if (!im) return;
-  if (im->host_running) (void)hipHostFree(im->host_running);
+  if (im->host_running) pinned_give(im->host_running);
   if (im->rounds_exec) (void)hipGraphExecDestroy(im->rounds_exec);
   if (im->cap_stream) (void)hipStreamDestroy(im->cap_stream);
-  if (im->aux_stream) (void)hipStreamDestroy(im->aux_stream);
   for (hipEvent_t& e : im->ev)
     if (e) (void)hipEventDestroy(e);
   delete im;

@@ -67,6 +67,10 @@ void set_tune(const bode_config& c, const Tune& t);
 void set_tune_candidate(const bode_config& c, const Tune& t);
 Tune get_tune(const bode_config& c);
 void set_thread_error(const std::string& m);
+// The process's second stream on the current device (created on first use,
+// default priority), shared by every handle: work on it is ordered against
+// the caller's stream by each handle's own events.
+hipError_t shared_aux_stream(hipStream_t* out);
 int autotune(const bode_config* cfg, const bode_problem* p, void* workspace,
              size_t workspace_bytes, void* stream);
 

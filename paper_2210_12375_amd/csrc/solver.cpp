@@ -51,15 +51,24 @@ std::mutex g_tune_mu;
 std::map<TuneKey, Tune> g_tune;
 bool g_tune_loaded = false;
 
+// The current device's architecture name, asked of the runtime once per
+// device (the query is slow, and every launch-shape lookup needs it).
+std::mutex g_arch_mu;
+std::map<int, std::string> g_arch;
+
 std::string device_arch() {
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  std::lock_guard<std::mutex> lk(g_arch_mu);
+  auto it = g_arch.find(dev);
+  if (it != g_arch.end()) return it->second;
   hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipGetDeviceProperties(&prop, dev) != hipSuccess)
-    return "unknown";
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
   std::string a = prop.gcnArchName;
   const size_t colon = a.find(':');
-  return colon == std::string::npos ? a : a.substr(0, colon);
+  if (colon != std::string::npos) a = a.substr(0, colon);
+  g_arch[dev] = a;
+  return a;
 }
 
 TuneKey tune_key(const bode_config& c) {
@@ -168,6 +177,10 @@ hipError_t aux_stream(hipStream_t* out) {
 }
 
 }  // namespace
+
+namespace bode {
+hipError_t shared_aux_stream(hipStream_t* out) { return aux_stream(out); }
+}  // namespace bode
 
 struct bode_solver {
   bode_config cfg{};
