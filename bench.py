@@ -459,15 +459,33 @@ def neural_accuracy(bd, W, n=256):
     1e-5, atol 1e-6) on its first n instances, per precision: max over the
     final state's components of |y - ref| / (rtol |ref| + atol) against the
     FP64 field solved at rtol 1e-11, atol 1e-13 (median and maximum over
-    instances)."""
+    instances).  The BF16 modes are also held against the FP64 solve of
+    their own model, whose weight matrices are rounded to BF16: the first
+    figure is then the model's rounding, the second the solver's error."""
     p = W.subset(W.neural_ode(), np.arange(n))
-    q = W.subset(p, np.arange(n))
-    q["rtol"][:] = 1e-11
-    q["atol"][:] = 1e-13
-    s = bd.Solver(bd.device_problem(q, "fp64"), method="dopri5",
-                  precision="fp64", rhs=bd.RHS_MLP).solve()
-    ref = s.y_final.cpu().numpy()
-    s.close()
+
+    def reference(weights_bf16):
+        q = W.subset(p, np.arange(n))
+        q["rtol"][:] = 1e-11
+        q["atol"][:] = 1e-13
+        if weights_bf16:  # the BF16 modes' model: W1 (state rows), W2, W3
+            q["mlp"] = dict(q["mlp"])  # rounded to the nearest BF16 value
+            for k in ("W1", "W2", "W3"):
+                w = np.array(q["mlp"][k], dtype=np.float32)
+                keep = w[-1:].copy() if k == "W1" else None  # time row
+                u = w.view(np.uint32).astype(np.uint64)
+                u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(
+                    np.uint32)
+                w = u.view(np.float32)
+                if keep is not None:
+                    w[-1:] = keep
+                q["mlp"][k] = w
+        s = bd.Solver(bd.device_problem(q, "fp64"), method="dopri5",
+                      precision="fp64", rhs=bd.RHS_MLP).solve()
+        r = s.y_final.cpu().numpy()
+        s.close()
+        return r
+    refs = {False: reference(False), True: reference(True)}
     out = {}
     for name, prec, kw in (("fp64", "fp64", {}), ("fp32", "fp32", {}),
                            ("bf16", "bf16", {}),
@@ -477,11 +495,16 @@ def neural_accuracy(bd, W, n=256):
         y = s.y_final.cpu().numpy().astype(np.float64)
         na = s.stats()["n_accepted"].cpu().numpy()
         s.close()
-        tol = p["rtol"][:, None] * np.abs(ref) + p["atol"][:, None]
-        e = (np.abs(y - ref) / tol).max(axis=1)
-        out[name] = {"err_in_tol_units_median": float(np.median(e)),
-                     "err_in_tol_units_max": float(e.max()),
-                     "accepted_steps_p50": float(np.median(na))}
+        r = {"accepted_steps_p50": float(np.median(na))}
+        for rounded, label in ((False, ""), (True, "_vs_bf16_weights")):
+            if rounded and prec != "bf16":
+                continue
+            ref = refs[rounded]
+            tol = p["rtol"][:, None] * np.abs(ref) + p["atol"][:, None]
+            e = (np.abs(y - ref) / tol).max(axis=1)
+            r["err_in_tol_units_median" + label] = float(np.median(e))
+            r["err_in_tol_units_max" + label] = float(e.max())
+        out[name] = r
     return out
 
 
