@@ -820,8 +820,9 @@ struct ModImpl {
   // which cannot be captured; graphs are replayed on the caller's)
   hipStream_t cap_stream = nullptr;
   // the discrete adjoint's events for its second stream (segment
-  // recomputation): start, ready[2], free[2], done
-  hipEvent_t ev[6] = {};
+  // recomputation): start, ready[2], free[2], done; and for its third
+  // (tape GEMMs): chunk written, GEMMs of tape half 0 / 1 done, all done
+  hipEvent_t ev[10] = {};
 };
 
 // Captures what enqueue(q) launches on the handle's capture stream q into an
@@ -2162,14 +2163,36 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   // Step n's cotangent chain: dense-output cotangents, the seven stage
   // VJPs (on the stored stage inputs Yh and layers Ah of segment step j,
   // or recomputing), and the chunk's parameter-gradient GEMMs.
+  // Tape GEMMs beside the cotangent chain: with room for two chunks of
+  // steps (matrix-core path), the tape's two halves alternate and each
+  // chunk's GEMMs run on a third stream while the next chunk's VJPs write
+  // the other half; a half is rewritten only after its GEMMs are done.
+  // Every GEMM adds into the slots on that one stream, in chunk order.
+  const bool ovl = im.mw.packedT != nullptr && b.C >= 2 && nmax > 1;
+  const int Cc = ovl ? b.C / 2 : b.C;
+  hipStream_t s3 = nullptr;
+  if (ovl) {
+    if (im.ev[0] == nullptr)
+      for (hipEvent_t& ev : im.ev)
+        if (e == hipSuccess && ev == nullptr)
+          e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = shared_aux_stream2(&s3);
+    if (e != hipSuccess) return e;
+  }
   auto back_step = [&](int n, const R* Yh, const float* Ah, int j,
                        int setup) -> hipError_t {
-    hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval,
-                       setup);
     // this step's place in its tape chunk (steps are taken in reverse)
-    const int slot = (nmax - 1 - n) % b.C;
+    const int idx = nmax - 1 - n, chunk = idx / Cc, slot_c = idx % Cc;
+    const int half = ovl ? (chunk & 1) : 0;
+    const int slot = half * Cc + slot_c;
     const long Bs = m.cnf ? 2L * m.B : (long)m.B;
     const long kbase = (long)slot * 7 * Bs;
+    if (ovl && slot_c == 0 && chunk >= 2) {
+      const hipError_t r = hipStreamWaitEvent(s, im.ev[7 + half], 0);
+      if (r != hipSuccess) return r;
+    }
+    hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval,
+                       setup);
     if (im.mw.packedT == nullptr) {
       // FMA kernels skip tiles without a step n: their cotangent rows must
       // read as zero (the matrix-core kernels write those zeros themselves)
@@ -2218,20 +2241,30 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       const hipError_t r = launch_vjp_steps_mfma(vs, s);
       if (r != hipSuccess) return r;
     }
-    if (slot == b.C - 1 || n == 0) {
+    if (slot_c == Cc - 1 || n == 0) {
       // parameter gradient of the chunk's steps: one GEMM per layer over
-      // its (slot + 1) * 7 * Bs tape rows
-      const long Kc = (long)(slot + 1) * 7 * Bs;
+      // its (slot_c + 1) * 7 * Bs tape rows, from the half's first row
+      const long Kc = (long)(slot_c + 1) * 7 * Bs;
+      const long r0 = (long)half * Cc * 7 * Bs;
       const int H = m.H, din = m.d_in, n0 = din + 1;
       const long o2 = (long)(n0 + 1) * H, o3 = o2 + (long)(H + 1) * H;
-      hipError_t r = launch_grad_gemm<R>(b.T1in, b.T1g, Kc, n0 + 1, H, b.G,
-                                         b.slots, b.P, 0, s);
+      hipStream_t sg = s;
+      hipError_t r = hipSuccess;
+      if (ovl) {
+        sg = s3;
+        r = hipEventRecord(im.ev[6], s);
+        if (r == hipSuccess) r = hipStreamWaitEvent(s3, im.ev[6], 0);
+      }
       if (r == hipSuccess)
-        r = launch_grad_gemm<R>(b.T2in, b.T2g, Kc, H + 1, H, b.G, b.slots,
-                                b.P, o2, s);
+        r = launch_grad_gemm<R>(b.T1in + r0 * (n0 + 1), b.T1g + r0 * H, Kc,
+                                n0 + 1, H, b.G, b.slots, b.P, 0, sg);
       if (r == hipSuccess)
-        r = launch_grad_gemm<R>(b.T3in, b.T3g, Kc, H + 1, din, b.G, b.slots,
-                                b.P, o3, s);
+        r = launch_grad_gemm<R>(b.T2in + r0 * (H + 1), b.T2g + r0 * H, Kc,
+                                H + 1, H, b.G, b.slots, b.P, o2, sg);
+      if (r == hipSuccess)
+        r = launch_grad_gemm<R>(b.T3in + r0 * (H + 1), b.T3g + r0 * din, Kc,
+                                H + 1, din, b.G, b.slots, b.P, o3, sg);
+      if (r == hipSuccess && ovl) r = hipEventRecord(im.ev[7 + half], s3);
       if (r != hipSuccess) return r;
     }
     return hipSuccess;
@@ -2328,6 +2361,11 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       if (e == hipSuccess) e = back_step(n, nullptr, nullptr, 0, 0);
       if (e != hipSuccess) return e;
     }
+  }
+  if (ovl) {  // the last chunk's GEMMs before the slots are summed
+    e = hipEventRecord(im.ev[9], s3);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, im.ev[9], 0);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(adj_finish<R>, lin_grid(BD), blk, 0, s, m, b, g_eval,
                      dy0);

@@ -71,6 +71,7 @@ void set_thread_error(const std::string& m);
 // default priority), shared by every handle: work on it is ordered against
 // the caller's stream by each handle's own events.
 hipError_t shared_aux_stream(hipStream_t* out);
+hipError_t shared_aux_stream2(hipStream_t* out);  // a third one
 int autotune(const bode_config* cfg, const bode_problem* p, void* workspace,
              size_t workspace_bytes, void* stream);
 

@@ -180,6 +180,28 @@ hipError_t aux_stream(hipStream_t* out) {
 
 namespace bode {
 hipError_t shared_aux_stream(hipStream_t* out) { return aux_stream(out); }
+
+// A third stream per device, created on first use (default priority).
+std::mutex g_aux2_mu;
+std::map<int, hipStream_t> g_aux2;
+
+hipError_t shared_aux_stream2(hipStream_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_aux2_mu);
+  auto it = g_aux2.find(dev);
+  if (it != g_aux2.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipStream_t s = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  g_aux2[dev] = s;
+  *out = s;
+  return hipSuccess;
+}
 }  // namespace bode
 
 struct bode_solver {
