@@ -533,10 +533,58 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 // depend on no other tile's, so its workgroup runs the stages in turn, the
 // cotangents passing between them through memory (the barrier orders them;
 // all of the tile's waves share the compute unit's cache).
+// The dense-output part of a step for the tile's PR instances, one
+// wavefront per row (the same arithmetic as the separate kernel).
+template <int PR, int WV>
+__device__ __forceinline__ void vjp_dense_rows(const MfmaVjpSteps& v) {
+  const VjpDense& d = v.dense;
+  const MfmaVjpArgs& a = v.st[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int B = a.B, D = a.D;
+  for (int r = wave; r < PR; r += WV) {
+    const int row = blockIdx.x * PR + r;
+    if (row >= B) continue;
+    const int n = d.step;
+    const bool on = n < d.nacc[row];
+    if (d.setup && lane == 0) {
+      d.act[row] = on ? kRunning : kSuccess;
+      d.bh[row] = on ? float(d.hacc[(long)row * d.cap + n]) : 0.f;
+      d.bt[row] = on ? d.tn[(long)row * (d.cap + 1) + n] : 0.0;
+    }
+    for (int c = lane; c < D; c += 64) {
+      a.lamn[(long)row * D + c] = 0.f;
+      for (int j = 0; j < 7; ++j) a.kap[((long)j * B + row) * D + c] = 0.f;
+    }
+    if (!on || d.E == 0) continue;
+    const double h = d.hacc[(long)row * d.cap + n];
+    const double t = d.tn[(long)row * (d.cap + 1) + n];
+    const int32_t* own = d.owner + (long)row * d.E;
+    for (int e = 0; e < d.E; ++e) {
+      if (own[e] != n) continue;
+      const float th = float((d.t_eval[(long)row * d.E + e] - t) / h);
+      float w[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+        w[j] = th * (d.P[j][0] +
+                     th * (d.P[j][1] + th * (d.P[j][2] + th * d.P[j][3])));
+      for (int c = lane; c < D; c += 64) {
+        const float g = d.g_eval[((long)row * d.E + e) * D + c];
+        for (int j = 0; j < 7; ++j)
+          a.kap[((long)j * B + row) * D + c] += float(h) * w[j] * g;
+        a.lamn[(long)row * D + c] += g;
+      }
+    }
+  }
+}
+
 template <class Op, int NTW, bool CNF, int WV>
 __global__ __launch_bounds__(64 * WV) __attribute__((
     amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_steps_kernel(MfmaVjpSteps v) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (v.dense.on) {
+    vjp_dense_rows<CNF ? 8 : 16, WV>(v);
+    __syncthreads();
+  }
   for (int i = 0; i < v.n; ++i) {
     vjp_tile<Op, NTW, CNF, WV>(v.st[i], smem_raw);
     __syncthreads();

@@ -104,9 +104,29 @@ hipError_t launch_vjp_mfma(const MfmaVjpArgs& a, hipStream_t s);
 
 // Up to seven stages of one step, each with its own arguments, in one
 // launch, in the order given (same shape and weights in every entry).
+// The step's dense-output cotangents and step view, formed by the
+// workgroup of each tile before its first stage (the discrete adjoint's
+// dense-output kernel, folded in): zero lambda_next and the seven kappa
+// rows, add h w_j(theta) g to kappa_j and g to lambda_next for every
+// evaluation time the step answers, and (setup) the step view act, bh, bt.
+struct VjpDense {
+  int on, setup, step, cap, E;
+  const int32_t* nacc;   // [B] accepted steps in the record
+  const double* hacc;    // [B, cap] accepted step sizes
+  const double* tn;      // [B, cap + 1] step start times
+  const int32_t* owner;  // [B, E] step answering each evaluation time
+  const double* t_eval;  // [B, E]
+  const float* g_eval;   // [B, E, D] cotangents of the outputs
+  float P[7][4];         // interpolant weights: w_j = th (P0 + th (P1 + ...))
+  int32_t* act;          // [B] step view (setup)
+  float* bh;
+  double* bt;
+};
+
 struct MfmaVjpSteps {
   MfmaVjpArgs st[7];
   int n;
+  VjpDense dense;
 };
 hipError_t launch_vjp_steps_mfma(const MfmaVjpSteps& v, hipStream_t s);
 

@@ -2191,8 +2191,37 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       const hipError_t r = hipStreamWaitEvent(s, im.ev[7 + half], 0);
       if (r != hipSuccess) return r;
     }
-    hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n, g_eval,
-                       setup);
+    // the seven stages in one launch on the matrix cores while the batch
+    // has few tiles (launches, not the tiles' work, set its pace; the
+    // dense-output part then runs in the same launch), else one launch
+    // each (a CNF step of 8192 instances: 16.9 ms one each, 18.9 in one)
+    [[maybe_unused]] MfmaVjpSteps vs{};
+    const bool steps = std::is_same<R, float>::value && im.mw.packedT &&
+                       few_tiles(m);
+    if (steps) {
+      if constexpr (std::is_same<R, float>::value) {
+        VjpDense& d = vs.dense;
+        d.on = 1;
+        d.setup = setup;
+        d.step = n;
+        d.cap = b.cap;
+        d.E = m.E;
+        d.nacc = b.nacc;
+        d.hacc = b.hacc;
+        d.tn = b.tn;
+        d.owner = b.owner;
+        d.t_eval = m.t_eval;
+        d.g_eval = g_eval;
+        for (int jj = 0; jj < 7; ++jj)
+          for (int q = 0; q < 4; ++q) d.P[jj][q] = float(M::P[jj][q]);
+        d.act = b.act;
+        d.bh = b.bh;
+        d.bt = b.bt;
+      }
+    } else {
+      hipLaunchKernelGGL((adj_dense<R, M>), rows_g, blk, 0, s, m, b, n,
+                         g_eval, setup);
+    }
     if (im.mw.packedT == nullptr) {
       // FMA kernels skip tiles without a step n: their cotangent rows must
       // read as zero (the matrix-core kernels write those zeros themselves)
@@ -2204,13 +2233,6 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       hipLaunchKernelGGL(fill_r<R>, lin_grid((long)m.d_in * rows), blk, 0, s,
                          b.T3g + kbase * m.d_in, (long)m.d_in * rows, R(0));
     }
-    // the seven stages in one launch on the matrix cores while the batch
-    // has few tiles (launches, not the tiles' work, set its pace), else one
-    // launch each (a CNF step of 8192 instances: 16.9 ms one each, 18.9 in
-    // one)
-    [[maybe_unused]] MfmaVjpSteps vs{};
-    const bool steps = std::is_same<R, float>::value && im.mw.packedT &&
-                       few_tiles(m);
     for (int st = 7; st >= 1; --st) {
       VjpSpec sp{};
       sp.s = st;
