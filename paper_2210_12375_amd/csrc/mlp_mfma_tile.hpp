@@ -421,13 +421,12 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
   // Two elements a thread at a time, every load first (at clamped rows):
   // the stage-input store may alias them as far as the compiler knows, so
   // loads after it would each wait for the one before.
-  float tv = 0.f;
-  if (tid < PR) {
-    const int row = r0 + tid < B ? r0 + tid : B - 1;
-    tv = float(a.t[row] + a.c * double(a.hs[row]));
-  }
+  // (The time column's t and h, and for the CNF the probe, are requested
+  // with the first elements' loads, so the prologue waits once.)
+  double tt = 0.0;
+  float th = 0.f;
   for (int i0 = tid; i0 < PR * D; i0 += 2 * (int)blockDim.x) {
-    float kv[2][6], yv[2], hv[2];
+    float kv[2][6], yv[2], hv[2], ev[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int idx = i0 + u * (int)blockDim.x;
@@ -438,6 +437,12 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
         kv[u][j] = j < a.n ? a.K[((long)a.kidx[j] * B + row) * D + c] : 0.f;
       yv[u] = a.y[(long)row * D + c];
       hv[u] = a.hs[row];
+      ev[u] = CNF ? a.eps[(long)row * D + c] : 0.f;
+    }
+    if (i0 == tid && tid < PR) {
+      const int row = r0 + tid < B ? r0 + tid : B - 1;
+      tt = a.t[row];
+      th = a.hs[row];
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -453,19 +458,16 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
         Yv = yv[u] + hv[u] * acc;
         if (a.write_y7) a.Y7[(long)row * D + c] = Yv;  // stage input out
       }
-      if (c < din) Op::put(Xh, PX, r * SX + c, Yv);
+      if (c < din) {
+        Op::put(Xh, PX, r * SX + c, Yv);
+        if (CNF) Op::put(Xh, PX, (PR + r) * SX + c, row < B ? ev[u] : 0.f);
+      }
     }
   }
+  const float tv = float(tt + a.c * double(th));
   for (int idx = tid; idx < RT * (dm.K1 - din); idx += blockDim.x) {
     const int r = idx / (dm.K1 - din), c = din + idx % (dm.K1 - din);
     Op::put(Xh, PX, r * SX + c, 0.f);
-  }
-  if (CNF) {
-    for (int idx = tid; idx < PR * din; idx += blockDim.x) {
-      const int r = idx / din, c = idx % din, row = r0 + r;
-      const float e = row < B ? a.eps[(long)row * D + c] : 0.f;
-      Op::put(Xh, PX, (PR + r) * SX + c, e);
-    }
   }
   if (tid < PR) tcol[tid] = r0 + tid < B ? tv : 0.f;
   __syncthreads();
