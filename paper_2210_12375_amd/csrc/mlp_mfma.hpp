@@ -60,6 +60,8 @@ struct MfmaArgs {
   float* act_out;
   // wavefronts per 16-row tile: 4 or 8 (0: the default for the width)
   int waves;
+  // the fused solve's stage slot of out (its stages kept in LDS)
+  int kslot;
 };
 
 MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,

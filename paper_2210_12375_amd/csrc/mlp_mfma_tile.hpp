@@ -376,9 +376,14 @@ __device__ __forceinline__ void gemm(f32x4 (&acc)[MT][NTW],
 // values stored to a.act_out when it is set; otherwise two blocks and no
 // layer store, which keeps the persistent solve kernels (the field, the
 // error norm and the controller in one body) within their registers.
-template <class Op, int NTW, bool CNF, int WV, bool DEEP = true>
+// KL: the stage values are a [7][rows][D] block in LDS at kl (the fused
+// solve keeps its tile's stages there) instead of the [7, B, D] array a.K;
+// the output is stage a.kslot of that block.
+template <class Op, int NTW, bool CNF, int WV, bool DEEP = true,
+          bool KL = false>
 __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
-                                           unsigned char* smem_raw) {
+                                           unsigned char* smem_raw,
+                                           float* kl = nullptr) {
   constexpr int MT = 1;
   typedef typename Op::A A;
   typedef typename Op::W W;
@@ -434,7 +439,9 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
       const int c = ii % D, row = r0 + ii / D < B ? r0 + ii / D : B - 1;
 #pragma unroll
       for (int j = 0; j < 6; ++j)
-        kv[u][j] = j < a.n ? a.K[((long)a.kidx[j] * B + row) * D + c] : 0.f;
+        kv[u][j] = j >= a.n ? 0.f
+                   : KL     ? kl[(a.kidx[j] * PR + ii / D) * D + c]
+                            : a.K[((long)a.kidx[j] * B + row) * D + c];
       yv[u] = a.y[(long)row * D + c];
       hv[u] = a.hs[row];
       ev[u] = CNF ? a.eps[(long)row * D + c] : 0.f;
@@ -593,7 +600,10 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
           const float v = acc[mt][t][i];
           if (!CNF || r < PR) {
             const int row = r0 + r;
-            if (row < B) a.out[(long)row * D + n] = v + b3n[t];
+            if (KL)
+              kl[(a.kslot * PR + r) * D + n] = v + b3n[t];
+            else if (row < B)
+              a.out[(long)row * D + n] = v + b3n[t];
           } else {
             // tangent row: eps_n * (dg/dz eps)_n, summed over the 16 columns
             const int pr = r - PR, row = r0 + pr;
@@ -613,7 +623,10 @@ __device__ __forceinline__ void field_tile(const MfmaArgs& a, int r0,
         const int row = r0 + pr;
         float q = 0.f;
         for (int nb = 0; nb < dm.nn3; ++nb) q += red[pr * dm.nn3 + nb];
-        if (row < B) a.out[(long)row * D + din] = -q;
+        if (KL)
+          kl[(a.kslot * PR + pr) * D + din] = -q;
+        else if (row < B)
+          a.out[(long)row * D + din] = -q;
       }
     }
   }

@@ -499,13 +499,28 @@ __global__ void mod_start_b(Mod<R> m, int probe) {
   m.hs[row] = last ? R(te - t) : h;
 }
 
+// Where a row's seven stage values are: stage j, column c at
+// base[j * sj + rr * D + c] — the [7, B, D] arrays in HBM (base = m.K,
+// sj = B D, rr = the row), or in the fused solve a tile's [7, rows, D]
+// block in LDS (KL: rr = the row's place in the tile).
+template <typename R>
+struct KView {
+  R* base;
+  long sj;
+  int rr;
+};
+
 // Error norm, controller, accept / reject, dense output, commit.
 // One row per W lanes (W = 64: a wavefront; W = 32: half of one, two rows
 // at a time); lane is the row's own lane index in [0, W).
-template <typename R, class M, bool KEEP, int W = 64>
-__device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
+template <typename R, class M, bool KEEP, int W = 64, bool KL = false>
+__device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane,
+                                           KView<R> kw = KView<R>{}) {
   if (row >= m.B || m.st.status[row] != kRunning) return;
   const int D = m.D, B = m.B;
+  if (!KL) kw = KView<R>{m.K, (long)B * D, row};
+  R* const kr = kw.base + (long)kw.rr * D;  // stage 0 of the row
+  const long sj = kw.sj;
   const R hs = m.hs[row];
   const R rt = R(m.rtol[row]), at = R(m.atol[row]);
   R acc = R(0);
@@ -525,9 +540,11 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
       f32x4 kv[7];
 #pragma unroll
       for (int j = 0; j < 7; ++j)
-        if (M::E[j] != 0.0 || j == 6)
-          kv[j] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(
-              reinterpret_cast<const float*>(m.K) + (long)j * B * D + o));
+        if (M::E[j] != 0.0 || j == 6) {
+          const f32x4* q = reinterpret_cast<const f32x4*>(
+              reinterpret_cast<const float*>(kr) + j * sj + lane * 4);
+          kv[j] = KL ? *q : __builtin_nontemporal_load(q);
+        }
       const f32x4 yv = __builtin_nontemporal_load(
           reinterpret_cast<const f32x4*>(
               reinterpret_cast<const float*>(m.st.y) + o));
@@ -553,7 +570,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
 #pragma unroll
       for (int j = 0; j < 7; ++j)
         if (M::E[j] != 0.0)
-          eq += R(M::E[j]) * m.K[((long)j * B + row) * D + c];
+          eq += R(M::E[j]) * kr[j * sj + c];
       eq *= hs;
       const R y = m.st.y[(long)row * D + c], yn = m.Y7[(long)row * D + c];
       const R sc = at + rt * rmax(rabs(y), rabs(yn));
@@ -606,7 +623,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
         for (int j = 0; j < 7; ++j)
           if (M::P[j][0] != 0.0 || M::P[j][1] != 0.0 || M::P[j][2] != 0.0 ||
               M::P[j][3] != 0.0)
-            s2 += w[j] * m.K[((long)j * B + row) * D + cc];
+            s2 += w[j] * kr[j * sj + cc];
         m.y_eval[((long)row * m.E + cursor) * D + cc] =
             m.st.y[(long)row * D + cc] + hs * s2;
       }
@@ -625,7 +642,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
 #pragma unroll
           for (int j = 0; j < 7; ++j)
             if (M::P[j][q] != 0.0)
-              s2 += R(M::P[j][q]) * m.K[((long)j * B + row) * D + cc];
+              s2 += R(M::P[j][q]) * kr[j * sj + cc];
           m.dk.q[((long)q * B + row) * D + cc] = hs * s2;
         }
       }
@@ -637,7 +654,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
       if (own) {
         const long o = (long)row * D + lane * 4;
         *reinterpret_cast<f32x4*>(reinterpret_cast<float*>(m.st.y) + o) = ynv;
-        *reinterpret_cast<f32x4*>(reinterpret_cast<float*>(m.K) + o) =
+        *reinterpret_cast<f32x4*>(reinterpret_cast<float*>(kr) + lane * 4) =
             k6v;  // FSAL
         if (ck)
           *reinterpret_cast<f32x4*>(
@@ -648,7 +665,7 @@ __device__ __forceinline__ void commit_row(const Mod<R>& m, int row, int lane) {
       for (int cc = lane; cc < D; cc += W) {
         const R yn = m.Y7[(long)row * D + cc];
         m.st.y[(long)row * D + cc] = yn;
-        m.K[(long)row * D + cc] = m.K[((long)6 * B + row) * D + cc];  // FSAL
+        kr[cc] = kr[6 * sj + cc];  // FSAL
         if (ck)
           m.ckpt[((long)row * m.ck_cap + nacc / m.ck_every) * D + cc] = yn;
       }
@@ -706,15 +723,28 @@ inline dim3 commit_grid(int B, int per) { return dim3((B + per - 1) / per); }
 struct FusedArgs {
   MfmaArgs st[6];  // stages 2..7: combination, node, output
   int budget;      // attempts per instance
+  int kl_off;      // KL: byte offset of the tile's stage block in LDS
 };
 
-template <class Op, int NTW, bool CNF, int WV, class M>
+// KL: the tile's seven stage values stay in LDS ([7][rows][D] after the
+// field's own LDS): stage inputs, outputs, error estimate, dense outputs and
+// FSAL never go through HBM; the FSAL stage is loaded at entry and stored
+// back at exit (a later launch, or a step slice, continues from it).
+template <class Op, int NTW, bool CNF, int WV, class M, bool KL>
 __global__ __launch_bounds__(64 * WV) void solve_fused_kernel(Mod<float> m,
                                                               FusedArgs f) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int PR = CNF ? 8 : 16;
   const int r0 = blockIdx.x * PR;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int D = m.D;
+  float* kl = KL ? reinterpret_cast<float*>(smem_raw + f.kl_off) : nullptr;
+  if (KL) {
+    for (int i = threadIdx.x; i < PR * D; i += blockDim.x) {
+      const int row = r0 + i / D;
+      kl[i] = row < m.B ? m.K[(long)row * D + i % D] : 0.f;
+    }
+  }
   __shared__ int active;
   for (int round = 0; round < f.budget; ++round) {
     __syncthreads();
@@ -726,7 +756,8 @@ __global__ __launch_bounds__(64 * WV) void solve_fused_kernel(Mod<float> m,
     __syncthreads();
     if (!active) break;
     for (int s = 0; s < 6; ++s) {
-      mtile::field_tile<Op, NTW, CNF, WV, false>(f.st[s], r0, smem_raw);
+      mtile::field_tile<Op, NTW, CNF, WV, false, KL>(f.st[s], r0, smem_raw,
+                                                      kl);
       __syncthreads();
     }
     // MLP: two rows per wavefront (32 lanes each) while D fits two columns
@@ -735,21 +766,38 @@ __global__ __launch_bounds__(64 * WV) void solve_fused_kernel(Mod<float> m,
     // wavefronts per SIMD
     if (!CNF && m.D <= 64) {
       for (int r = 2 * wave + (lane >> 5); r < PR; r += 2 * WV)
-        commit_row<float, M, false, 32>(m, r0 + r, lane & 31);
+        commit_row<float, M, false, 32, KL>(m, r0 + r, lane & 31,
+                                            KView<float>{kl, PR * D, r});
     } else {
       for (int r = wave; r < PR; r += WV)
-        commit_row<float, M, false>(m, r0 + r, lane);
+        commit_row<float, M, false, 64, KL>(m, r0 + r, lane,
+                                            KView<float>{kl, PR * D, r});
+    }
+  }
+  if (KL) {  // the FSAL stage back to HBM
+    __syncthreads();
+    for (int i = threadIdx.x; i < PR * D; i += blockDim.x) {
+      const int row = r0 + i / D;
+      if (row < m.B) m.K[(long)row * D + i % D] = kl[i];
     }
   }
 }
 
 template <class Op, int NTW, bool CNF, int WV, class M>
-hipError_t fused_t(const Mod<float>& m, const FusedArgs& f, hipStream_t s) {
+hipError_t fused_t(const Mod<float>& m, FusedArgs f, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
   const size_t sm = mtile::mfma_smem<Op, NTW, CNF, WV>(m.d_in);
   if (sm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((solve_fused_kernel<Op, NTW, CNF, WV, M>),
-                     dim3((m.B + PR - 1) / PR), dim3(64 * WV), sm, s, m, f);
+  // the stage block in LDS while it fits beside the field's LDS
+  f.kl_off = (int)((sm + 15) / 16 * 16);
+  const size_t smk = f.kl_off + sizeof(float) * 7 * PR * (size_t)m.D;
+  if (smk <= 65536)
+    hipLaunchKernelGGL((solve_fused_kernel<Op, NTW, CNF, WV, M, true>),
+                       dim3((m.B + PR - 1) / PR), dim3(64 * WV), smk, s, m,
+                       f);
+  else
+    hipLaunchKernelGGL((solve_fused_kernel<Op, NTW, CNF, WV, M, false>),
+                       dim3((m.B + PR - 1) / PR), dim3(64 * WV), sm, s, m, f);
   return hipGetLastError();
 }
 
@@ -1062,6 +1110,7 @@ hipError_t run_fused(const ModImpl& im, const Mod<float>& m, int budget,
     StageSpec sp = stage_spec<M>(st);
     if (st == 6) sp.yout = m.Y7;
     f.st[st - 1] = stage_args(im, m, sp, m.K + (size_t)st * m.B * m.D);
+    f.st[st - 1].kslot = st;
   }
   f.budget = budget;
   return fused_launch<M>(m, f, im.mw.f32, im.mw.plain, s);
