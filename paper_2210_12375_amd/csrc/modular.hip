@@ -141,7 +141,8 @@ constexpr int kSlots = 128;  // most k-splits of a parameter-gradient GEMM
 // gradient is one GEMM per layer over a whole chunk, so a small batch's
 // GEMMs run on enough tape rows to fill the chip (one step of a
 // 1024-instance MLP is 7168 rows, 0.9 GFLOP); at most 8 steps and at most
-// 512 MiB of tape (a 8192-instance CNF step alone is ~1 GB: one step).
+// 512 MiB of tape, but two steps where one fits in 1 GiB (a 8192-instance
+// CNF step is 0.96 GB).
 inline int tape_steps(const bode_config& c, long B, int din, int H,
                       size_t elem) {
   const long rows = 7L * B * (c.rhs == BODE_RHS_CNF ? 2 : 1);
@@ -149,6 +150,9 @@ inline int tape_steps(const bode_config& c, long B, int din, int H,
       (size_t)rows * (size_t)((din + 2) + H + 2 * (H + 1) + H + din) * elem;
   const size_t budget = size_t(512) << 20;
   int steps = per_step > 0 ? (int)(budget / per_step) : 1;
+  // two steps at least while a step's tape is at most 1 GiB, so that one
+  // step's parameter-gradient GEMMs can run beside the next one's VJPs
+  if (steps < 2 && per_step <= (size_t(1) << 30)) steps = 2;
   if (steps > 8) steps = 8;
   if (steps > c.record_cap) steps = c.record_cap;
   return steps < 1 ? 1 : steps;
