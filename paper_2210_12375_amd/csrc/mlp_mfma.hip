@@ -97,9 +97,13 @@ hipError_t launch_t(const MfmaArgs& a, const MfmaSteps* v, hipStream_t s) {
 // workgroups per compute unit): it spills a few registers, but the second
 // workgroup hides more of the three-layer dependent chain (measured 156 ->
 // 133 us per stage for 8192 instances).
-template <class Op, int NTW, bool CNF, int WV>
+// CL: the step's stage cotangents kappa and lambda_next of the tile's rows
+// are a [8][rows][D] block in LDS at cl (slots 0-6: kappa_1..7, slot 7:
+// lambda_next) instead of the arrays a.kap, a.lamn; lambda stays in HBM.
+template <class Op, int NTW, bool CNF, int WV, bool CL = false>
 __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
-                                         unsigned char* smem_raw) {
+                                         unsigned char* smem_raw,
+                                         float* cl = nullptr) {
   typedef typename Op::A A;
   typedef typename Op::W W;
   constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 16 * WV,
@@ -202,11 +206,12 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
       const int ii = idx < PR * din ? idx : 0;
       const int r = ii / din, c = ii % din;
       const long o = (long)(r0 + r < B ? r0 + r : B - 1) * D;
+      const float* ks = CL ? cl + ((a.s - 1) * PR + r) * D : a.kap_s + o;
       Yr[e] = a.Y[o + c];
-      Kz[e] = a.kap_s[o + c];
+      Kz[e] = ks[c];
       if (CNF) {
         Er[e] = a.eps[o + c];
-        Kl[e] = a.kap_s[o + din];
+        Kl[e] = ks[din];
       }
     }
 #pragma unroll
@@ -394,13 +399,13 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
   for (int idx = tid; idx < PR * din; idx += blockDim.x) {
     const int r = idx / din, c = idx % din, row = r0 + r;
     const bool o = on(row);
-    const float kz = o ? a.kap_s[(long)row * D + c] : 0.f;
+    const float* ks =
+        CL ? cl + ((a.s - 1) * PR + r) * D : a.kap_s + (long)row * D;
+    const float kz = o ? ks[c] : 0.f;
     Op::put(Xh, PX, r * SX + c, kz);
     if (row < B) a.T3g[(kb + row) * din + c] = kz;
     if (CNF) {
-      const float g = o ? -a.kap_s[(long)row * D + din] *
-                              a.eps[(long)row * D + c]
-                        : 0.f;
+      const float g = o ? -ks[din] * a.eps[(long)row * D + c] : 0.f;
       Op::put(Xh, PX, (PR + r) * SX + c, g);
       if (row < B) a.T3g[(kb + B + row) * din + c] = g;
     }
@@ -490,10 +495,12 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
       const long o = (long)row * D + c;
       h[u] = a.bh[row];
       lam[u] = a.lam[o];
-      lamn[u] = a.lamn[o];
+      lamn[u] = CL ? cl[(7 * PR + r) * D + c] : a.lamn[o];
 #pragma unroll
       for (int j = 0; j < 6; ++j)
-        if (j < a.n) kp[u][j] = a.kap[((long)a.kidx[j] * B + row) * D + c];
+        if (j < a.n)
+          kp[u][j] = CL ? cl[(a.kidx[j] * PR + r) * D + c]
+                        : a.kap[((long)a.kidx[j] * B + row) * D + c];
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -511,12 +518,19 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
         a.lam[o] = mu;
       }
       const float ln = lamn[u] + mu;
-      a.lamn[o] = ln;
+      if (CL)
+        cl[(7 * PR + r) * D + c] = ln;
+      else
+        a.lamn[o] = ln;
 #pragma unroll
       for (int j = 0; j < 6; ++j)
-        if (j < a.n)
-          a.kap[((long)a.kidx[j] * B + row) * D + c] =
-              kp[u][j] + h[u] * a.coef[j] * mu;
+        if (j < a.n) {
+          const float v = kp[u][j] + h[u] * a.coef[j] * mu;
+          if (CL)
+            cl[(a.kidx[j] * PR + r) * D + c] = v;
+          else
+            a.kap[((long)a.kidx[j] * B + row) * D + c] = v;
+        }
       if (a.s == 1) a.lam[o] = ln;
     }
   }
@@ -535,8 +549,9 @@ __global__ __launch_bounds__(64 * WV) __attribute__((
 // all of the tile's waves share the compute unit's cache).
 // The dense-output part of a step for the tile's PR instances, one
 // wavefront per row (the same arithmetic as the separate kernel).
-template <int PR, int WV>
-__device__ __forceinline__ void vjp_dense_rows(const MfmaVjpSteps& v) {
+template <int PR, int WV, bool CL>
+__device__ __forceinline__ void vjp_dense_rows(const MfmaVjpSteps& v,
+                                               float* cl) {
   const VjpDense& d = v.dense;
   const MfmaVjpArgs& a = v.st[0];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -551,9 +566,16 @@ __device__ __forceinline__ void vjp_dense_rows(const MfmaVjpSteps& v) {
       d.bh[row] = on ? float(d.hacc[(long)row * d.cap + n]) : 0.f;
       d.bt[row] = on ? d.tn[(long)row * (d.cap + 1) + n] : 0.0;
     }
+    // kappa_j of (row, c): the tile's LDS block or HBM
+    auto kap = [&](int j, int c) -> float& {
+      return CL ? cl[(j * PR + r) * D + c] : a.kap[((long)j * B + row) * D + c];
+    };
+    auto lamn = [&](int c) -> float& {
+      return CL ? cl[(7 * PR + r) * D + c] : a.lamn[(long)row * D + c];
+    };
     for (int c = lane; c < D; c += 64) {
-      a.lamn[(long)row * D + c] = 0.f;
-      for (int j = 0; j < 7; ++j) a.kap[((long)j * B + row) * D + c] = 0.f;
+      lamn(c) = 0.f;
+      for (int j = 0; j < 7; ++j) kap(j, c) = 0.f;
     }
     if (!on || d.E == 0) continue;
     const double h = d.hacc[(long)row * d.cap + n];
@@ -569,24 +591,27 @@ __device__ __forceinline__ void vjp_dense_rows(const MfmaVjpSteps& v) {
                      th * (d.P[j][1] + th * (d.P[j][2] + th * d.P[j][3])));
       for (int c = lane; c < D; c += 64) {
         const float g = d.g_eval[((long)row * d.E + e) * D + c];
-        for (int j = 0; j < 7; ++j)
-          a.kap[((long)j * B + row) * D + c] += float(h) * w[j] * g;
-        a.lamn[(long)row * D + c] += g;
+        for (int j = 0; j < 7; ++j) kap(j, c) += float(h) * w[j] * g;
+        lamn(c) += g;
       }
     }
   }
 }
 
-template <class Op, int NTW, bool CNF, int WV>
+// CL: the cotangents stay in LDS through the step (v.cl_off: their block's
+// byte offset; the dense-output part must run in the same launch, since it
+// is what clears and seeds them).
+template <class Op, int NTW, bool CNF, int WV, bool CL>
 __global__ __launch_bounds__(64 * WV) __attribute__((
     amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_steps_kernel(MfmaVjpSteps v) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* cl = CL ? reinterpret_cast<float*>(smem_raw + v.cl_off) : nullptr;
   if (v.dense.on) {
-    vjp_dense_rows<CNF ? 8 : 16, WV>(v);
+    vjp_dense_rows<CNF ? 8 : 16, WV, CL>(v, cl);
     __syncthreads();
   }
   for (int i = 0; i < v.n; ++i) {
-    vjp_tile<Op, NTW, CNF, WV>(v.st[i], smem_raw);
+    vjp_tile<Op, NTW, CNF, WV, CL>(v.st[i], smem_raw, cl);
     __syncthreads();
   }
 }
@@ -597,10 +622,18 @@ hipError_t launch_vjp_t(const MfmaVjpArgs& a, const MfmaVjpSteps* v,
   constexpr int PR = CNF ? 8 : 16;
   const size_t sm = mfma_smem<Op, NTW, CNF, WV>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  if (v != nullptr)
-    hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV>),
-                       dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, *v);
-  else
+  if (v != nullptr) {
+    // the cotangent block in LDS while it fits beside the kernel's LDS
+    MfmaVjpSteps w = *v;
+    w.cl_off = (int)((sm + 15) / 16 * 16);
+    const size_t smc = w.cl_off + sizeof(float) * 8 * PR * (size_t)a.D;
+    if (w.dense.on && smc <= 65536)
+      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, true>),
+                         dim3((a.B + PR - 1) / PR), dim3(64 * WV), smc, s, w);
+    else
+      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, false>),
+                         dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, w);
+  } else
     hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF, WV>),
                        dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
   return hipGetLastError();

@@ -129,6 +129,7 @@ struct MfmaVjpSteps {
   MfmaVjpArgs st[7];
   int n;
   VjpDense dense;
+  int cl_off;  // set by the launcher
 };
 hipError_t launch_vjp_steps_mfma(const MfmaVjpSteps& v, hipStream_t s);
 
