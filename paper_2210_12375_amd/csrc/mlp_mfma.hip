@@ -60,12 +60,14 @@ __global__ __launch_bounds__(64 * WV) void field_mfma_kernel(MfmaArgs a) {
 // Several stage evaluations of one step in one launch, in order: a tile's
 // stage inputs depend only on its own rows' earlier stages, which pass
 // between the tile's waves through memory (the barrier orders them).
-template <class Op, int NTW, bool CNF, int WV>
+// KL: the stage values stay in LDS (v.kl_off) between the stages.
+template <class Op, int NTW, bool CNF, int WV, bool KL>
 __global__ __launch_bounds__(64 * WV) void field_steps_kernel(MfmaSteps v) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* kl = KL ? reinterpret_cast<float*>(smem_raw + v.kl_off) : nullptr;
   for (int i = 0; i < v.n; ++i) {
-    field_tile<Op, NTW, CNF, WV>(v.st[i], blockIdx.x * (CNF ? 8 : 16),
-                                 smem_raw);
+    field_tile<Op, NTW, CNF, WV, true, KL>(v.st[i], blockIdx.x * (CNF ? 8 : 16),
+                                           smem_raw, kl);
     __syncthreads();
   }
 }
@@ -75,10 +77,17 @@ hipError_t launch_t(const MfmaArgs& a, const MfmaSteps* v, hipStream_t s) {
   constexpr int PR = CNF ? 8 : 16;
   const size_t sm = mfma_smem<Op, NTW, CNF, WV>(a.din);
   if (sm > 65536) return hipErrorInvalidValue;
-  if (v != nullptr)
-    hipLaunchKernelGGL((field_steps_kernel<Op, NTW, CNF, WV>),
-                       dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, *v);
-  else
+  if (v != nullptr) {
+    MfmaSteps w = *v;
+    w.kl_off = (int)((sm + 15) / 16 * 16);
+    const size_t smk = w.kl_off + sizeof(float) * 7 * PR * (size_t)a.D;
+    if (w.kl && smk <= 65536)
+      hipLaunchKernelGGL((field_steps_kernel<Op, NTW, CNF, WV, true>),
+                         dim3((a.B + PR - 1) / PR), dim3(64 * WV), smk, s, w);
+    else
+      hipLaunchKernelGGL((field_steps_kernel<Op, NTW, CNF, WV, false>),
+                         dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, w);
+  } else
     hipLaunchKernelGGL((field_mfma_kernel<Op, NTW, CNF, WV>),
                        dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, a);
   return hipGetLastError();
@@ -100,10 +109,67 @@ hipError_t launch_t(const MfmaArgs& a, const MfmaSteps* v, hipStream_t s) {
 // CL: the step's stage cotangents kappa and lambda_next of the tile's rows
 // are a [8][rows][D] block in LDS at cl (slots 0-6: kappa_1..7, slot 7:
 // lambda_next) instead of the arrays a.kap, a.lamn; lambda stays in HBM.
-template <class Op, int NTW, bool CNF, int WV, bool CL = false>
-__device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
-                                         unsigned char* smem_raw,
-                                         float* cl = nullptr) {
+// Elements of a tile's [PR, din] block each thread handles, for din up to
+// DMAX.
+template <int PR, int WV, int DMAX = 256>
+constexpr int vjp_ne() {
+  return (PR * DMAX + 64 * WV - 1) / (64 * WV);
+}
+
+// A stage's stored values the VJP of a tile reads from memory: the stage
+// input Y (NE elements a thread) and the two stored hidden layers at this
+// lane's accumulator elements.
+template <int NE, int NTW>
+struct VjpFront {
+  float Y[NE];
+  float keep[2][NTW][4];
+};
+
+// Requests them, at clamped rows and unconditionally, so that no load waits
+// on a branch (rows without the step are zeroed where they are used).
+template <bool CNF, int WV, int NE, int NTW>
+__device__ __forceinline__ void vjp_front_load(const MfmaVjpArgs& a,
+                                               VjpFront<NE, NTW>& f) {
+  constexpr int PR = CNF ? 8 : 16, H = NTW * 16 * WV;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rq = (lane >> 4) * 4, col = lane & 15;
+  const int din = a.din, D = a.D, B = a.B, r0 = blockIdx.x * PR;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int idx = tid + e * (int)blockDim.x;
+    const int ii = idx < PR * din ? idx : 0;
+    const int r = ii / din, c = ii % din;
+    f.Y[e] = a.Y[(long)(r0 + r < B ? r0 + r : B - 1) * D + c];
+  }
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer)
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      const int n = (wave * NTW + t) * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rq + i;
+        const bool primal = !CNF || row < PR;
+        const int g = r0 + (primal ? row : row - PR);
+        f.keep[layer][t][i] =
+            a.act_in[((long)((g < B ? g : B - 1) + (primal ? 0 : B)) * 2 +
+                      layer) * H + n];
+      }
+    }
+}
+
+// PF (stored layers, steps launch, din <= 64): the stage's VjpFront was requested
+// during the previous stage (or before the launch's dense-output part) into
+// *pf, and this stage requests nxt's (the last stage: its own again) into it
+// once its own are used, so their memory latency overlaps this stage's last phase; the
+// tile's step view (running rows, t, h) is read from memory at the first
+// stage only.
+template <class Op, int NTW, bool CNF, int WV, bool CL = false,
+          bool PF = false>
+__device__ __forceinline__ void vjp_tile(
+    const MfmaVjpArgs& a, unsigned char* smem_raw, float* cl = nullptr,
+    VjpFront<vjp_ne<CNF ? 8 : 16, WV, 64>(), NTW>* pf = nullptr,
+    const MfmaVjpArgs& nxt = MfmaVjpArgs{}, bool first = true) {
   typedef typename Op::A A;
   typedef typename Op::W W;
   constexpr int RT = 16, PR = CNF ? 8 : 16, H = NTW * 16 * WV,
@@ -123,6 +189,8 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
   float* MU = reinterpret_cast<float*>(Xh);  // [PR][din], after S2 is read
   __shared__ int any_running;
   __shared__ int onr[PR];  // the tile's rows that have this step
+  __shared__ double tstep[PR];  // their t_n and h_n
+  __shared__ float hstep[PR];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = blockIdx.x * PR;
@@ -137,14 +205,16 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
   WRing<Op, NTW, PD, H / 32> r2;
   WRing<Op, 4, PD4, H / 32> r1;
   if (ahead) r3.start(wt, dt.nk3, dt.nn3, wave * NTW, 1, NTW, lane);
-  if (tid == 0) any_running = 0;
-  __syncthreads();
-  if (tid < PR) {
-    const int o = r0 + tid < B && a.act[r0 + tid] == kRunning;
-    onr[tid] = o;
-    if (o) any_running = 1;
+  if (!PF || first) {
+    if (tid == 0) any_running = 0;
+    __syncthreads();
+    if (tid < PR) {
+      const int o = r0 + tid < B && a.act[r0 + tid] == kRunning;
+      onr[tid] = o;
+      if (o) any_running = 1;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const long kb = a.kb;
   const long l1 = din + 2;  // tape row widths: T1in din + 2, T2in/T3in H + 1
   if (!any_running) {
@@ -195,11 +265,16 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
     // layer is recomputed, so nothing here waits on anything but memory,
     // and every load of the kernel's front half is issued at once (stage
     // input, cotangent, probe, stored layers, time) before the first store.
-    constexpr int NE = (PR * 256 + 64 * WV - 1) / (64 * WV);
-    float Yr[NE], Kz[NE], Er[NE], Kl[NE];
-    // (loads at clamped rows, unconditionally, so none waits on a branch;
-    // rows without this step are then read as zero: their stored values
-    // come from stale states)
+    constexpr int NE = vjp_ne<PR, WV, PF ? 64 : 256>();
+    VjpFront<NE, NTW> fl;
+    VjpFront<NE, NTW>* fp = &fl;
+    if constexpr (PF)
+      fp = pf;
+    else
+      vjp_front_load<CNF, WV>(a, fl);
+    VjpFront<NE, NTW>& f = *fp;
+    float(&Yr)[NE] = f.Y;
+    float Kz[NE], Er[NE], Kl[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const int idx = tid + e * (int)blockDim.x;
@@ -207,28 +282,29 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
       const int r = ii / din, c = ii % din;
       const long o = (long)(r0 + r < B ? r0 + r : B - 1) * D;
       const float* ks = CL ? cl + ((a.s - 1) * PR + r) * D : a.kap_s + o;
-      Yr[e] = a.Y[o + c];
       Kz[e] = ks[c];
       if (CNF) {
         Er[e] = a.eps[o + c];
         Kl[e] = ks[din];
       }
     }
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer)
-#pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        const int n = (wave * NTW + t) * 16 + col;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = rq + i;
-          const bool primal = !CNF || row < PR;
-          const int g = r0 + (primal ? row : row - PR);
-          keep[layer][t][i] =
-              a.act_in[((long)((g < B ? g : B - 1) + (primal ? 0 : B)) * 2 +
-                        layer) * H + n];
-        }
-      }
+    // the time column's t and h (clamped row), kept in LDS for the row
+    // updates (and, PF, for the later stages)
+    const int trow = r0 + (tid < PR ? tid : 0) < B ? r0 + (tid < PR ? tid : 0)
+                                                  : B - 1;
+    double tb;
+    float hb;
+    if (!PF || first) {
+      tb = a.bt[trow];
+      hb = a.bh[trow];
+    } else {
+      tb = tstep[tid < PR ? tid : 0];
+      hb = hstep[tid < PR ? tid : 0];
+    }
+    if (tid < PR) {
+      tstep[tid] = tb;
+      hstep[tid] = hb;
+    }
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const int idx = tid + e * (int)blockDim.x;
@@ -242,11 +318,12 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
         for (int i = 0; i < 4; ++i) {
           const int row = rq + i;
           const int pr = !CNF || row < PR ? row : row - PR;
-          if (r0 + pr >= B || !onr[pr]) keep[layer][t][i] = 0.f;
+          keep[layer][t][i] =
+              r0 + pr >= B || !onr[pr] ? 0.f : f.keep[layer][t][i];
         }
-    float tv = 0.f;
-    if (tid < PR && r0 + tid < B && onr[tid])
-      tv = float(a.bt[r0 + tid] + a.c * double(a.bh[r0 + tid]));
+    const float tv = tid < PR && r0 + tid < B && onr[tid]
+                         ? float(tb + a.c * double(hb))
+                         : 0.f;
     // layer-1 inputs and the cotangent gbar (kappa_z on primal rows,
     // -kappa_l eps on tangent rows) into the tape; gbar into LDS
 #pragma unroll
@@ -335,6 +412,7 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
     const float tv =
         on(row) ? float(a.bt[row] + a.c * double(a.bh[row])) : 0.f;
     tcol[r] = tv;
+    hstep[r] = row < B ? a.bh[row] : 0.f;
     if (row < B) {
       a.T1in[(kb + row) * l1 + din] = tv;
       a.T1in[(kb + row) * l1 + din + 1] = 1.f;
@@ -484,6 +562,10 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
   // a thread at a time: every value they read is loaded before any is
   // written (they write distinct addresses, which the compiler cannot
   // know, so it would otherwise wait for each load in turn)
+  // (PF: the next stage's front is requested here, ahead of the updates,
+  // which then read only LDS but for lambda at stage 7; unconditionally, so
+  // that the front just used is no longer live)
+  if constexpr (PF) vjp_front_load<CNF, WV>(nxt, *pf);
   constexpr int NU = CNF ? 1 : 2;
   for (int i0 = tid; i0 < PR * D; i0 += NU * (int)blockDim.x) {
     float lam[NU], lamn[NU], kp[NU][6], h[NU];
@@ -493,8 +575,8 @@ __device__ __forceinline__ void vjp_tile(const MfmaVjpArgs& a,
       const int r = idx / D, c = idx % D, row = r0 + r;
       if (idx >= PR * D || !on(row) || a.mu_out != nullptr) continue;
       const long o = (long)row * D + c;
-      h[u] = a.bh[row];
-      lam[u] = a.lam[o];
+      h[u] = hstep[r];
+      if (a.s == 7) lam[u] = a.lam[o];
       lamn[u] = CL ? cl[(7 * PR + r) * D + c] : a.lamn[o];
 #pragma unroll
       for (int j = 0; j < 6; ++j)
@@ -601,17 +683,22 @@ __device__ __forceinline__ void vjp_dense_rows(const MfmaVjpSteps& v,
 // CL: the cotangents stay in LDS through the step (v.cl_off: their block's
 // byte offset; the dense-output part must run in the same launch, since it
 // is what clears and seeds them).
-template <class Op, int NTW, bool CNF, int WV, bool CL>
+// PF: the stage fronts are requested a stage ahead (the first one before
+// the dense-output part); only with the stored layers and the LDS block.
+template <class Op, int NTW, bool CNF, int WV, bool CL, bool PF>
 __global__ __launch_bounds__(64 * WV) __attribute__((
     amdgpu_waves_per_eu(CNF ? 4 : 1))) void vjp_steps_kernel(MfmaVjpSteps v) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* cl = CL ? reinterpret_cast<float*>(smem_raw + v.cl_off) : nullptr;
+  VjpFront<vjp_ne<CNF ? 8 : 16, WV, 64>(), NTW> f;
+  if constexpr (PF) vjp_front_load<CNF, WV>(v.st[0], f);
   if (v.dense.on) {
     vjp_dense_rows<CNF ? 8 : 16, WV, CL>(v, cl);
     __syncthreads();
   }
   for (int i = 0; i < v.n; ++i) {
-    vjp_tile<Op, NTW, CNF, WV, CL>(v.st[i], smem_raw, cl);
+    vjp_tile<Op, NTW, CNF, WV, CL, PF>(v.st[i], smem_raw, cl, &f,
+                                       v.st[i + 1 < v.n ? i + 1 : i], i == 0);
     __syncthreads();
   }
 }
@@ -627,11 +714,18 @@ hipError_t launch_vjp_t(const MfmaVjpArgs& a, const MfmaVjpSteps* v,
     MfmaVjpSteps w = *v;
     w.cl_off = (int)((sm + 15) / 16 * 16);
     const size_t smc = w.cl_off + sizeof(float) * 8 * PR * (size_t)a.D;
-    if (w.dense.on && smc <= 65536)
-      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, true>),
+    bool stored = true;  // every stage reads its stored layers
+    for (int i = 0; i < w.n; ++i) stored = stored && w.st[i].act_in;
+    // (the fronts a stage ahead: while the kernel's registers allow)
+    constexpr bool kPF = !CNF && NTW <= 2;
+    if (w.dense.on && smc <= 65536 && stored && kPF && a.din <= 64)
+      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, true, kPF>),
+                         dim3((a.B + PR - 1) / PR), dim3(64 * WV), smc, s, w);
+    else if (w.dense.on && smc <= 65536)
+      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, true, false>),
                          dim3((a.B + PR - 1) / PR), dim3(64 * WV), smc, s, w);
     else
-      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, false>),
+      hipLaunchKernelGGL((vjp_steps_kernel<Op, NTW, CNF, WV, false, false>),
                          dim3((a.B + PR - 1) / PR), dim3(64 * WV), sm, s, w);
   } else
     hipLaunchKernelGGL((vjp_mfma_kernel<Op, NTW, CNF, WV>),

@@ -136,6 +136,10 @@ hipError_t launch_vjp_steps_mfma(const MfmaVjpSteps& v, hipStream_t s);
 struct MfmaSteps {
   MfmaArgs st[7];
   int n;
+  // kl = 1: the caller reads none of the stage values, which may then stay
+  // in the tile's LDS ([7][rows][D] at byte kl_off, st[i].kslot each stage's
+  // slot) instead of going to st[i].out; kl_off is set by the launcher
+  int kl, kl_off;
 };
 hipError_t launch_field_steps_mfma(const MfmaSteps& v, hipStream_t s);
 // both travel as kernel arguments

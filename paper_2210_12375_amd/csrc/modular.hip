@@ -2169,7 +2169,9 @@ hipError_t stages_store(ModImpl& im, Mod<R> v, Back<R>& b, int j,
     sp.act_out = b.Ast + ((size_t)j * 7 + st) * AH;
     if constexpr (std::is_same<R, float>::value) {
       if (im.mw.packed != nullptr && few_tiles(v)) {  // the seven in one
-        fs.st[fs.n++] = stage_args(im, v, sp, b.Ks + (size_t)st * BD);
+        fs.st[fs.n] = stage_args(im, v, sp, b.Ks + (size_t)st * BD);
+        fs.st[fs.n++].kslot = st;
+        fs.kl = 1;  // the stage values are read only by the later stages
         continue;
       }
     }
