@@ -18,36 +18,58 @@ using namespace mtile;
 __device__ __forceinline__ void cvt(uint16_t& d, float v) { d = f2bf(v); }
 __device__ __forceinline__ void cvt(float& d, float v) { d = v; }
 
-// Packs M = W (trans = 0) or W^T into the fragment layout of mtile.
+// One weight matrix to pack: M = W (trans = 0) or W^T into the fragment
+// layout of mtile (W row-major with leading dimension ldw, K rows of M).
 template <typename W>
-__global__ void pack_kernel(W* dst, const float* Wm, int K, int ldw, int nk,
-                            int nn, int trans) {
-  const long total = (long)nk * nn * 512;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
+struct PackJob {
+  W* dst;
+  const float* Wm;
+  int K, ldw, nk, nn, trans;
+};
+
+template <typename W>
+__device__ void pack_one(const PackJob<W>& j, int blk, int nblk) {
+  const long total = (long)j.nk * j.nn * 512;
+  for (long e = blk * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)nblk * blockDim.x) {
     const int i = e & 7, l = (e >> 3) & 63;
     const long f = e >> 9;
-    const int kb = int(f / nn), nb = int(f % nn);
+    const int kb = int(f / j.nn), nb = int(f % j.nn);
     const int k = kb * 32 + (l >> 4) * 8 + i, n = nb * 16 + (l & 15);
-    const long src = trans ? (long)n * ldw + k : (long)k * ldw + n;
-    cvt(dst[e], k < K ? Wm[src] : 0.f);
+    const long src = j.trans ? (long)n * j.ldw + k : (long)k * j.ldw + n;
+    cvt(j.dst[e], k < j.K ? j.Wm[src] : 0.f);
   }
 }
 
-__global__ void fvec_kernel(float* f, const float* W1, const float* b1,
-                            const float* b2, const float* b3, int din, int H) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < 3 * H + din;
-       j += gridDim.x * blockDim.x) {
+// The three layers (and, with the transposed copies, their transposes)
+// and the vector block (b1, W1's time row, b2, b3) in one launch: grid y
+// selects the job, the last one being the vector block.
+template <typename W>
+__global__ void pack_weights_kernel(PackJob<W> j0, PackJob<W> j1,
+                                    PackJob<W> j2, PackJob<W> j3,
+                                    PackJob<W> j4, PackJob<W> j5, int njobs,
+                                    float* f, const float* W1, const float* b1,
+                                    const float* b2, const float* b3, int din,
+                                    int H) {
+  const int y = blockIdx.y;
+  if (y < njobs) {
+    const PackJob<W>& j = y == 0 ? j0 : y == 1 ? j1 : y == 2 ? j2
+                        : y == 3 ? j3 : y == 4 ? j4 : j5;
+    pack_one(j, blockIdx.x, gridDim.x);
+    return;
+  }
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < 3 * H + din;
+       c += gridDim.x * blockDim.x) {
     float v;
-    if (j < H)
-      v = b1[j];
-    else if (j < 2 * H)
-      v = W1[(long)din * H + (j - H)];  // time row of W1
-    else if (j < 3 * H)
-      v = b2[j - 2 * H];
+    if (c < H)
+      v = b1[c];
+    else if (c < 2 * H)
+      v = W1[(long)din * H + (c - H)];  // time row of W1
+    else if (c < 3 * H)
+      v = b2[c - 2 * H];
     else
-      v = b3[j - 3 * H];
-    f[j] = v;
+      v = b3[c - 3 * H];
+    f[c] = v;
   }
 }
 
@@ -735,26 +757,26 @@ hipError_t launch_vjp_t(const MfmaVjpArgs& a, const MfmaVjpSteps* v,
 
 template <class Op>
 hipError_t pack_all(const MfmaWeights& w, int din, int H, const float* W1,
-                    const float* W2, const float* W3, hipStream_t s) {
+                    const float* b1, const float* W2, const float* b2,
+                    const float* W3, const float* b3, hipStream_t s) {
   typedef typename Op::W W;
   const Dims d = dims(din, H);
   W* p = static_cast<W*>(w.packed);
-  hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, p, W1, din,
-                     H, d.nk1, d.nn1, 0);
-  hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, p + d.off2,
-                     W2, H, H, d.nk2, d.nn2, 0);
-  hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, p + d.off3,
-                     W3, H, din, d.nk3, d.nn3, 0);
+  PackJob<W> j[6] = {{p, W1, din, H, d.nk1, d.nn1, 0},
+                     {p + d.off2, W2, H, H, d.nk2, d.nn2, 0},
+                     {p + d.off3, W3, H, din, d.nk3, d.nn3, 0}};
+  int n = 3;
   if (w.packedT != nullptr) {
     const DimsT t = dims_t(din, H);
     W* q = static_cast<W*>(w.packedT);
-    hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, q, W3, din,
-                       din, t.nk3, t.nn3, 1);
-    hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, q + t.off2,
-                       W2, H, H, t.nk2, t.nn2, 1);
-    hipLaunchKernelGGL(pack_kernel<W>, dim3(256), dim3(256), 0, s, q + t.off1,
-                       W1, H, H, t.nk1, t.nn1, 1);
+    j[3] = {q, W3, din, din, t.nk3, t.nn3, 1};
+    j[4] = {q + t.off2, W2, H, H, t.nk2, t.nn2, 1};
+    j[5] = {q + t.off1, W1, H, H, t.nk1, t.nn1, 1};
+    n = 6;
   }
+  hipLaunchKernelGGL(pack_weights_kernel<W>, dim3(128, n + 1), dim3(256), 0,
+                     s, j[0], j[1], j[2], j[3], j[4], j[5], n, w.fvec, W1, b1,
+                     b2, b3, din, H);
   return hipGetLastError();
 }
 
@@ -831,12 +853,8 @@ hipError_t mfma_pack_weights(const MfmaWeights& w, int din, int H,
                              const float* W1, const float* b1, const float* W2,
                              const float* b2, const float* W3, const float* b3,
                              hipStream_t s) {
-  const hipError_t e = w.f32 ? pack_all<F32>(w, din, H, W1, W2, W3, s)
-                             : pack_all<Bf3>(w, din, H, W1, W2, W3, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fvec_kernel, dim3(8), dim3(256), 0, s, w.fvec, W1, b1, b2,
-                     b3, din, H);
-  return hipGetLastError();
+  return w.f32 ? pack_all<F32>(w, din, H, W1, b1, W2, b2, W3, b3, s)
+               : pack_all<Bf3>(w, din, H, W1, b1, W2, b2, W3, b3, s);
 }
 
 MfmaArgs mfma_args(int B, int D, int din, int H, int cnf, const int32_t* status,

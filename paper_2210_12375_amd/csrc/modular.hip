@@ -137,12 +137,13 @@ struct Back {
 
 constexpr int kSlots = 128;  // most k-splits of a parameter-gradient GEMM
 
-// Steps per chunk of the discrete adjoint's gradient tape: the parameter
-// gradient is one GEMM per layer over a whole chunk, so a small batch's
-// GEMMs run on enough tape rows to fill the chip (one step of a
-// 1024-instance MLP is 7168 rows, 0.9 GFLOP); at most 8 steps and at most
-// 512 MiB of tape, but two steps where one fits in 1 GiB (a 8192-instance
-// CNF step is 0.96 GB).
+// Steps the discrete adjoint's gradient tape holds: the parameter gradient
+// is one GEMM per layer over a chunk of steps, so a small batch's GEMMs run
+// on enough tape rows to fill the chip (one step of a 1024-instance MLP is
+// 7168 rows, 0.9 GFLOP); the tape is two halves whose chunks alternate, so
+// at most 4 steps (chunks of two: the last chunk's GEMMs, which follow the
+// last VJP, stay short) and at most 512 MiB, but two steps where one fits
+// in 1 GiB (a 8192-instance CNF step is 0.96 GB).
 inline int tape_steps(const bode_config& c, long B, int din, int H,
                       size_t elem) {
   const long rows = 7L * B * (c.rhs == BODE_RHS_CNF ? 2 : 1);
@@ -153,7 +154,7 @@ inline int tape_steps(const bode_config& c, long B, int din, int H,
   // two steps at least while a step's tape is at most 1 GiB, so that one
   // step's parameter-gradient GEMMs can run beside the next one's VJPs
   if (steps < 2 && per_step <= (size_t(1) << 30)) steps = 2;
-  if (steps > 8) steps = 8;
+  if (steps > 4) steps = 4;
   if (steps > c.record_cap) steps = c.record_cap;
   return steps < 1 ? 1 : steps;
 }
@@ -2188,8 +2189,6 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
                       const R* g_final, R* dy0, R* dtheta, hipStream_t s) {
   const long BD = (long)m.B * m.D;
   const dim3 rows_g((m.B + 3) / 4), blk(256);
-  hipLaunchKernelGGL(fill_r<R>, lin_grid(b.G * b.P), blk, 0, s, b.slots,
-                     (long)b.G * b.P, R(0));
   if (im.mw.packedT == nullptr) {
     // tape inputs of tiles no step writes must be finite (they meet 0); the
     // matrix-core VJP kernels write zeros into those rows themselves
@@ -2225,6 +2224,12 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   // Every GEMM adds into the slots on that one stream, in chunk order.
   const bool ovl = im.mw.packedT != nullptr && b.C >= 2 && nmax > 1;
   const int Cc = ovl ? b.C / 2 : b.C;
+  // k-split slots: a GEMM over K tape rows uses at most K / 256 of them, so
+  // only those of the largest chunk are cleared and summed
+  const long Bs7 = 7L * (m.cnf ? 2 : 1) * m.B;
+  const int G = (int)std::min<long>(b.G, std::max<long>(1, Cc * Bs7 / 256));
+  hipLaunchKernelGGL(fill_r<R>, lin_grid((long)G * b.P), blk, 0, s, b.slots,
+                     (long)G * b.P, R(0));
   hipStream_t s3 = nullptr;
   if (ovl) {
     if (im.ev[0] == nullptr)
@@ -2334,13 +2339,13 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
       }
       if (r == hipSuccess)
         r = launch_grad_gemm<R>(b.T1in + r0 * (n0 + 1), b.T1g + r0 * H, Kc,
-                                n0 + 1, H, b.G, b.slots, b.P, 0, sg);
+                                n0 + 1, H, G, b.slots, b.P, 0, sg);
       if (r == hipSuccess)
         r = launch_grad_gemm<R>(b.T2in + r0 * (H + 1), b.T2g + r0 * H, Kc,
-                                H + 1, H, b.G, b.slots, b.P, o2, sg);
+                                H + 1, H, G, b.slots, b.P, o2, sg);
       if (r == hipSuccess)
         r = launch_grad_gemm<R>(b.T3in + r0 * (H + 1), b.T3g + r0 * din, Kc,
-                                H + 1, din, b.G, b.slots, b.P, o3, sg);
+                                H + 1, din, G, b.slots, b.P, o3, sg);
       if (r == hipSuccess && ovl) r = hipEventRecord(im.ev[7 + half], s3);
       if (r != hipSuccess) return r;
     }
@@ -2446,7 +2451,7 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
   }
   hipLaunchKernelGGL(adj_finish<R>, lin_grid(BD), blk, 0, s, m, b, g_eval,
                      dy0);
-  hipLaunchKernelGGL(reduce_slots<R>, lin_grid(b.P), blk, 0, s, b.slots, b.G,
+  hipLaunchKernelGGL(reduce_slots<R>, lin_grid(b.P), blk, 0, s, b.slots, G,
                      b.P, dtheta);
   return hipGetLastError();
 }
