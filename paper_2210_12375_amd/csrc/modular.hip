@@ -1856,22 +1856,21 @@ __global__ __launch_bounds__(256) void grad_gemm(const R* Tin, const R* Tg,
 // pass through LDS 16 tape rows at a time (contiguous runs of features).
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+// Workgroup bx of the product (tile bx / S, k-split bx % S); As, Bs: LDS of
+// at least 16 (32 WM + 16) and 16 (32 WN + 16) floats.
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void grad_gemm_mfma(
-    const float* Tin, const float* Tg, long K, int M, int N, int S,
-    float* slots, long P, long off, long sin, long sg, long sslot) {
+__device__ __forceinline__ void grad_gemm_tile(int bx, const float* Tin,
+                                               const float* Tg, long K, int M,
+                                               int N, int S, float* slots,
+                                               long P, long off, float* As,
+                                               float* Bs) {
   constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16;
-  Tin += blockIdx.y * sin;
-  Tg += blockIdx.y * sg;
-  slots += blockIdx.y * sslot;
   // row pitch 16 floats past the tile: the four lane groups of an operand
   // read land 16 banks apart
   constexpr int LA = TM + 16, LB = TN + 16;
   constexpr int NA = TK * TM / 256, NB = TK * TN / 256;  // loads per thread
-  __shared__ float As[TK * LA];
-  __shared__ float Bs[TK * LB];
   const int tiles_n = (N + TN - 1) / TN;
-  const int tile = blockIdx.x / S, split = blockIdx.x % S;
+  const int tile = bx / S, split = bx % S;
   const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
   const long kc = ((K + S - 1) / S + TK - 1) / TK * TK;
   const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
@@ -1943,6 +1942,57 @@ __global__ __launch_bounds__(256) void grad_gemm_mfma(
         const int n = n0 + wn + j * 16 + lr;
         if (m < M && n < N) slot[(long)m * N + n] += acc[i][j][v];
       }
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void grad_gemm_mfma(
+    const float* Tin, const float* Tg, long K, int M, int N, int S,
+    float* slots, long P, long off, long sin, long sg, long sslot) {
+  __shared__ float As[16 * (32 * WM + 16)];
+  __shared__ float Bs[16 * (32 * WN + 16)];
+  grad_gemm_tile<WM, WN>(blockIdx.x, Tin + blockIdx.y * sin,
+                         Tg + blockIdx.y * sg, K, M, N, S,
+                         slots + blockIdx.y * sslot, P, off, As, Bs);
+}
+
+// Tile shapes of the FP32 matrix-core gradient products.
+enum GemmShape { kG14, kG41, kG42, kG34, kG44 };
+
+// The products of one chunk (one per layer, different shapes) in one
+// launch: workgroups [0, nblk[0]) are product 0's, and so on, each
+// product's workgroups exactly those of its own launch.
+struct GemmGroup {
+  const float* Tin[3];
+  const float* Tg[3];
+  int M[3], N[3], S[3], shape[3], nblk[3];
+  long off[3];
+  long K, P;
+  float* slots;
+};
+
+__global__ __launch_bounds__(256) void grad_gemm_group(GemmGroup g) {
+  __shared__ float As[16 * (128 + 16)];
+  __shared__ float Bs[16 * (128 + 16)];
+  int b = blockIdx.x, j = 0;
+  while (j < 2 && b >= g.nblk[j]) b -= g.nblk[j++];
+  const float *Tin = g.Tin[j], *Tg = g.Tg[j];
+  const int M = g.M[j], N = g.N[j], S = g.S[j];
+  switch (g.shape[j]) {
+    case kG14:
+      grad_gemm_tile<1, 4>(b, Tin, Tg, g.K, M, N, S, g.slots, g.P, g.off[j], As, Bs);
+      break;
+    case kG41:
+      grad_gemm_tile<4, 1>(b, Tin, Tg, g.K, M, N, S, g.slots, g.P, g.off[j], As, Bs);
+      break;
+    case kG42:
+      grad_gemm_tile<4, 2>(b, Tin, Tg, g.K, M, N, S, g.slots, g.P, g.off[j], As, Bs);
+      break;
+    case kG34:
+      grad_gemm_tile<3, 4>(b, Tin, Tg, g.K, M, N, S, g.slots, g.P, g.off[j], As, Bs);
+      break;
+    default:
+      grad_gemm_tile<4, 4>(b, Tin, Tg, g.K, M, N, S, g.slots, g.P, g.off[j], As, Bs);
+  }
 }
 
 // Large layers (both sides >= 256, long tapes): 256 x 256 tiles of C over
@@ -2034,6 +2084,49 @@ __global__ __launch_bounds__(512) void grad_gemm_big(
   if (brow && tid < TT && n0 + tid < N) slot[(long)M * N + n0 + tid] += bacc;
 }
 
+// Launch shape of a parameter-gradient product C[M, N] = sum over K tape
+// rows: tile shape (FP32 matrix cores: 32 WM x 32 WN), narrow where the
+// layer has few inputs or outputs, so little of a tile is padding (a
+// 257 x 64 layer on 128 x 64 tiles, 66 x 256 on 96 x 128); k-splits: a few
+// rounds of workgroups over the chip (about 2048 over all nb products, so
+// the last round's tail is short), each split at least 256 tape rows long,
+// at most the S slots there are.  big: 256 x 256 tiles (layers with at
+// least 256 weight rows and columns and long tapes).
+struct GemmPlan {
+  int shape, tiles, splits;
+  bool big;
+  int tb, sb;
+};
+
+inline GemmPlan plan_grad_gemm(bool f32, long K, int M, int N, int S,
+                               int nb) {
+  GemmPlan p{};
+  int wm = 4, wn = 4;
+  p.shape = kG44;
+  if (M <= 32) wm = 1, p.shape = kG14;
+  else if (N <= 32) wn = 1, p.shape = kG41;
+  else if (N <= 64 && M > 64) wn = 2, p.shape = kG42;
+  else if (M <= 96 && N > 64) wm = 3, p.shape = kG34;
+  const int tm = !f32 ? 64 : 32 * wm, tn = !f32 ? 64 : 32 * wn;
+  p.tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
+  int splits = (2048 + p.tiles * nb - 1) / (p.tiles * nb);
+  const long by_k = K / 256 > 0 ? K / 256 : 1;
+  if (splits > by_k) splits = (int)by_k;
+  if (splits > S) splits = S;
+  p.splits = splits;
+  p.big = f32 && M - 1 >= 256 && N >= 256 && K * nb >= 65536;
+  if (p.big) {
+    // weight rows on 256 x 256 tiles; the bias row is the last input
+    // feature and rides with the first row of tiles
+    p.tb = ((M - 1 + 255) / 256) * ((N + 255) / 256);
+    int sb = (1024 + p.tb * nb - 1) / (p.tb * nb);
+    if (sb > by_k) sb = (int)by_k;
+    if (sb > S) sb = S;
+    p.sb = sb;
+  }
+  return p;
+}
+
 // nb > 1: nb products of the same shape in one launch (grid y), product j
 // reading Tin + j sin and Tg + j sg and adding into its own S slots at
 // slots + j sslot (sslot >= S P).
@@ -2043,59 +2136,85 @@ hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int nb = 1, long sin = 0, long sg = 0,
                             long sslot = 0) {
   if (nb < 1 || (nb > 1 && sslot < (long)S * P)) return hipErrorInvalidValue;
-  // tile shape (FP32 matrix cores: 32 WM x 32 WN): narrow where the layer
-  // has few inputs or outputs, so little of a tile is padding (a 257 x 64
-  // layer on 128 x 64 tiles, 66 x 256 on 96 x 128)
   const bool f32 = std::is_same<R, float>::value;
-  int wm = 4, wn = 4;
-  if (M <= 32) wm = 1;
-  else if (N <= 32) wn = 1;
-  else if (N <= 64 && M > 64) wn = 2;
-  else if (M <= 96 && N > 64) wm = 3;
-  const int tm = !f32 ? 64 : 32 * wm, tn = !f32 ? 64 : 32 * wn;
-  const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
-  // k-splits: a few rounds of workgroups over the chip (about 2048 over
-  // all nb products, so the last round's tail is short), each split at
-  // least 256 tape rows long, at most the S slots there are
-  int splits = (2048 + tiles * nb - 1) / (tiles * nb);
-  const long by_k = K / 256 > 0 ? K / 256 : 1;
-  if (splits > by_k) splits = (int)by_k;
-  if (splits > S) splits = S;
-  const dim3 g(tiles * splits, nb), blk(256);
+  const GemmPlan pl = plan_grad_gemm(f32, K, M, N, S, nb);
+  const dim3 g(pl.tiles * pl.splits, nb), blk(256);
+  const int splits = pl.splits;
   if constexpr (std::is_same<R, float>::value) {
-    if (M - 1 >= 256 && N >= 256 && K * nb >= 65536) {
-      // weight rows on 256 x 256 tiles; the bias row is the last input
-      // feature and rides with the first row of tiles
-      const int Mw = M - 1;
-      const int tb = ((Mw + 255) / 256) * ((N + 255) / 256);
-      int sb = (1024 + tb * nb - 1) / (tb * nb);
-      if (sb > by_k) sb = (int)by_k;
-      if (sb > S) sb = S;
-      hipLaunchKernelGGL(grad_gemm_big, dim3(tb * sb, nb), dim3(512), 0, s,
-                         Tin, M, Tg, K, Mw, N, sb, slots, P, off, sin, sg,
-                         sslot);
+    if (pl.big) {
+      hipLaunchKernelGGL(grad_gemm_big, dim3(pl.tb * pl.sb, nb), dim3(512), 0,
+                         s, Tin, M, Tg, K, M - 1, N, pl.sb, slots, P, off, sin,
+                         sg, sslot);
       return hipGetLastError();
     }
-    if (wm == 1)
-      hipLaunchKernelGGL((grad_gemm_mfma<1, 4>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off, sin, sg, sslot);
-    else if (wn == 1)
-      hipLaunchKernelGGL((grad_gemm_mfma<4, 1>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off, sin, sg, sslot);
-    else if (wn == 2)
-      hipLaunchKernelGGL((grad_gemm_mfma<4, 2>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off, sin, sg, sslot);
-    else if (wm == 3)
-      hipLaunchKernelGGL((grad_gemm_mfma<3, 4>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off, sin, sg, sslot);
-    else
-      hipLaunchKernelGGL((grad_gemm_mfma<4, 4>), g, blk, 0, s, Tin, Tg, K, M,
-                         N, splits, slots, P, off, sin, sg, sslot);
+    switch (pl.shape) {
+      case kG14:
+        hipLaunchKernelGGL((grad_gemm_mfma<1, 4>), g, blk, 0, s, Tin, Tg, K,
+                           M, N, splits, slots, P, off, sin, sg, sslot);
+        break;
+      case kG41:
+        hipLaunchKernelGGL((grad_gemm_mfma<4, 1>), g, blk, 0, s, Tin, Tg, K,
+                           M, N, splits, slots, P, off, sin, sg, sslot);
+        break;
+      case kG42:
+        hipLaunchKernelGGL((grad_gemm_mfma<4, 2>), g, blk, 0, s, Tin, Tg, K,
+                           M, N, splits, slots, P, off, sin, sg, sslot);
+        break;
+      case kG34:
+        hipLaunchKernelGGL((grad_gemm_mfma<3, 4>), g, blk, 0, s, Tin, Tg, K,
+                           M, N, splits, slots, P, off, sin, sg, sslot);
+        break;
+      default:
+        hipLaunchKernelGGL((grad_gemm_mfma<4, 4>), g, blk, 0, s, Tin, Tg, K,
+                           M, N, splits, slots, P, off, sin, sg, sslot);
+    }
   } else {
     hipLaunchKernelGGL(grad_gemm<R>, g, blk, 0, s, Tin, Tg, K, M, N, splits,
                        slots, P, off, sin, sg, sslot);
   }
   return hipGetLastError();
+}
+
+// The three layers' products of one chunk (tape rows K): grouped, one
+// launch of grad_gemm_group where none takes the 256 x 256 tiles (each product with
+// exactly the workgroups and k-splits of its own launch, so the slots hold
+// the same sums), else one launch each.
+template <typename R>
+hipError_t launch_grad_gemm3(const R* const Tin[3], const R* const Tg[3],
+                             long K, const int M[3], const int N[3], int S,
+                             R* slots, long P, const long off[3],
+                             hipStream_t s, bool grouped) {
+  if constexpr (std::is_same<R, float>::value) {
+    GemmGroup g{};
+    bool ok = true;
+    long nblk = 0;
+    for (int j = 0; j < 3; ++j) {
+      const GemmPlan pl = plan_grad_gemm(true, K, M[j], N[j], S, 1);
+      ok = ok && !pl.big;
+      g.Tin[j] = Tin[j];
+      g.Tg[j] = Tg[j];
+      g.M[j] = M[j];
+      g.N[j] = N[j];
+      g.S[j] = pl.splits;
+      g.shape[j] = pl.shape;
+      g.nblk[j] = pl.tiles * pl.splits;
+      g.off[j] = off[j];
+      nblk += g.nblk[j];
+    }
+    if (ok && grouped) {
+      g.K = K;
+      g.P = P;
+      g.slots = slots;
+      hipLaunchKernelGGL(grad_gemm_group, dim3((unsigned)nblk), dim3(256), 0,
+                         s, g);
+      return hipGetLastError();
+    }
+  }
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < 3 && e == hipSuccess; ++j)
+    e = launch_grad_gemm<R>(Tin[j], Tg[j], K, M[j], N[j], S, slots, P, off[j],
+                            s);
+  return e;
 }
 
 // dtheta = sum of the slots in slot order (deterministic).
@@ -2337,15 +2456,18 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
         r = hipEventRecord(im.ev[6], s);
         if (r == hipSuccess) r = hipStreamWaitEvent(s3, im.ev[6], 0);
       }
-      if (r == hipSuccess)
-        r = launch_grad_gemm<R>(b.T1in + r0 * (n0 + 1), b.T1g + r0 * H, Kc,
-                                n0 + 1, H, G, b.slots, b.P, 0, sg);
-      if (r == hipSuccess)
-        r = launch_grad_gemm<R>(b.T2in + r0 * (H + 1), b.T2g + r0 * H, Kc,
-                                H + 1, H, G, b.slots, b.P, o2, sg);
-      if (r == hipSuccess)
-        r = launch_grad_gemm<R>(b.T3in + r0 * (H + 1), b.T3g + r0 * din, Kc,
-                                H + 1, din, G, b.slots, b.P, o3, sg);
+      if (r == hipSuccess) {
+        const R* const ti[3] = {b.T1in + r0 * (n0 + 1), b.T2in + r0 * (H + 1),
+                                b.T3in + r0 * (H + 1)};
+        const R* const tg[3] = {b.T1g + r0 * H, b.T2g + r0 * H,
+                                b.T3g + r0 * din};
+        const int gm[3] = {n0 + 1, H + 1, H + 1}, gn[3] = {H, H, din};
+        const long go[3] = {0, o2, o3};
+        // (the last chunk's products, which nothing runs beside, in one
+        // launch; the others one layer at a time, beside the VJPs)
+        r = launch_grad_gemm3<R>(ti, tg, Kc, gm, gn, G, b.slots, b.P, go, sg,
+                                 n == 0);
+      }
       if (r == hipSuccess && ovl) r = hipEventRecord(im.ev[7 + half], s3);
       if (r != hipSuccess) return r;
     }
