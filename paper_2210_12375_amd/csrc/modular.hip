@@ -2084,6 +2084,127 @@ __global__ __launch_bounds__(512) void grad_gemm_big(
   if (brow && tid < TT && n0 + tid < N) slot[(long)M * N + n0 + tid] += bacc;
 }
 
+// BF16 mode's large tape products on the BF16 matrix cores.  Each FP32
+// tape value x is split into two BF16 terms, hi (x's top 16 bits) and lo
+// (the top 16 bits of the exact residual x - hi), and C += Ah Bh + Ah Bl +
+// Al Bh (v_mfma_f32_16x16x32_bf16, FP32 accumulation): the dropped Al Bl
+// and the truncated residuals leave about 2^-16 of each product, far below
+// the BF16 weights' own rounding.  Tiles of 128 (m) x 256 (n) of C over 8
+// wavefronts (2 x 4, each 64 x 64 = 4 x 4 MFMA tiles); 32 tape rows a
+// stage, both operands stored in LDS k-contiguous ([m][k] and [n][k], row
+// pitch 40 halves) so that a lane's eight k values are one 16-byte read;
+// each thread loads eight rows of one feature (coalesced over features)
+// and writes its eight k values as one 16-byte store per term; the next
+// stage's rows are loaded during the products.  C rows are all M input
+// features (the bias feature included), as in grad_gemm_mfma.
+constexpr int kBgM = 128, kBgN = 256, kBgK = 32, kBgP = kBgK + 8;
+
+__device__ __forceinline__ void split_store8(uint16_t* hi, uint16_t* lo,
+                                             const float (&v)[8]) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t w[2], r[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t u = __float_as_uint(v[2 * j + q]);
+      const float res = v[2 * j + q] - __uint_as_float(u & 0xffff0000u);
+      w[q] = u >> 16;
+      r[q] = __float_as_uint(res) >> 16;
+    }
+    h[j] = w[0] | (w[1] << 16);
+    l[j] = r[0] | (r[1] << 16);
+  }
+  *reinterpret_cast<uint4*>(hi) = make_uint4(h[0], h[1], h[2], h[3]);
+  *reinterpret_cast<uint4*>(lo) = make_uint4(l[0], l[1], l[2], l[3]);
+}
+
+__global__ __launch_bounds__(512) void grad_gemm_bf16(
+    const float* Tin, const float* Tg, long K, int M, int N, int S,
+    float* slots, long P, long off) {
+  __shared__ __align__(16) uint16_t Ah[kBgM * kBgP];
+  __shared__ __align__(16) uint16_t Al[kBgM * kBgP];
+  __shared__ __align__(16) uint16_t Bh[kBgN * kBgP];
+  __shared__ __align__(16) uint16_t Bl[kBgN * kBgP];
+  const int tiles_n = (N + kBgN - 1) / kBgN;
+  const int tile = blockIdx.x / S, split = blockIdx.x % S;
+  const int m0 = (tile / tiles_n) * kBgM, n0 = (tile % tiles_n) * kBgN;
+  const long kc = ((K + S - 1) / S + kBgK - 1) / kBgK * kBgK;
+  const long k0 = split * kc, k1 = k0 + kc < K ? k0 + kc : K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 2) * 64, wn = (wave & 3) * 64;
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  // staging: A feature tid % 128, k group tid / 128 (eight rows); B features
+  // tid % 256 and the k groups tid / 256 and tid / 256 + 2
+  const int am = tid % kBgM, ag = tid / kBgM;
+  const int bn = tid % kBgN, bg = tid / kBgN;
+  float ra[8], rb[2][8];
+  auto fetch = [&](long kk) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const long k = kk + ag * 8 + j;
+      const int m = m0 + am;
+      ra[j] = (m < M && k < k1) ? Tin[k * M + m] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const long k = kk + (bg + 2 * q) * 8 + j;
+        const int n = n0 + bn;
+        rb[q][j] = (n < N && k < k1) ? Tg[k * N + n] : 0.f;
+      }
+  };
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (k0 < k1) fetch(k0);
+  for (long kk = k0; kk < k1; kk += kBgK) {
+    split_store8(Ah + am * kBgP + ag * 8, Al + am * kBgP + ag * 8, ra);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      split_store8(Bh + bn * kBgP + (bg + 2 * q) * 8,
+                   Bl + bn * kBgP + (bg + 2 * q) * 8, rb[q]);
+    __syncthreads();
+    if (kk + kBgK < k1) fetch(kk + kBgK);
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = (wm + i * 16 + r) * kBgP + kq;
+      ah[i] = mtile::lds8(Ah + o);
+      al[i] = mtile::lds8(Al + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = (wn + j * 16 + r) * kBgP + kq;
+      bh[j] = mtile::lds8(Bh + o);
+      bl[j] = mtile::lds8(Bl + o);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = mtile::mfma(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = mtile::mfma(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = mtile::mfma(al[i], bh[j], acc[i][j]);
+      }
+    __syncthreads();
+  }
+  float* slot = slots + (long)split * P + off;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + v;
+        const int n = n0 + wn + j * 16 + r;
+        if (m < M && n < N) slot[(long)m * N + n] += acc[i][j][v];
+      }
+}
+
 // Launch shape of a parameter-gradient product C[M, N] = sum over K tape
 // rows: tile shape (FP32 matrix cores: 32 WM x 32 WN), narrow where the
 // layer has few inputs or outputs, so little of a tile is padding (a
@@ -2129,18 +2250,30 @@ inline GemmPlan plan_grad_gemm(bool f32, long K, int M, int N, int S,
 
 // nb > 1: nb products of the same shape in one launch (grid y), product j
 // reading Tin + j sin and Tg + j sg and adding into its own S slots at
-// slots + j sslot (sslot >= S P).
+// slots + j sslot (sslot >= S P).  bf16: BF16 mode, whose large products
+// (the 256 x 256 case) go to the split-BF16 matrix cores.
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int S, R* slots, long P, long off, hipStream_t s,
                             int nb = 1, long sin = 0, long sg = 0,
-                            long sslot = 0) {
+                            long sslot = 0, bool bf16 = false) {
   if (nb < 1 || (nb > 1 && sslot < (long)S * P)) return hipErrorInvalidValue;
   const bool f32 = std::is_same<R, float>::value;
   const GemmPlan pl = plan_grad_gemm(f32, K, M, N, S, nb);
   const dim3 g(pl.tiles * pl.splits, nb), blk(256);
   const int splits = pl.splits;
   if constexpr (std::is_same<R, float>::value) {
+    if (pl.big && bf16 && nb == 1) {
+      // 128 x 256 tiles over all M features, about 1024 workgroups
+      const int tb = ((M + kBgM - 1) / kBgM) * ((N + kBgN - 1) / kBgN);
+      const long by_k = K / 256 > 0 ? K / 256 : 1;
+      int sb = (1024 + tb - 1) / tb;
+      if (sb > by_k) sb = (int)by_k;
+      if (sb > S) sb = S;
+      hipLaunchKernelGGL(grad_gemm_bf16, dim3(tb * sb), dim3(512), 0, s, Tin,
+                         Tg, K, M, N, sb, slots, P, off);
+      return hipGetLastError();
+    }
     if (pl.big) {
       hipLaunchKernelGGL(grad_gemm_big, dim3(pl.tb * pl.sb, nb), dim3(512), 0,
                          s, Tin, M, Tg, K, M - 1, N, pl.sb, slots, P, off, sin,
@@ -2183,7 +2316,7 @@ template <typename R>
 hipError_t launch_grad_gemm3(const R* const Tin[3], const R* const Tg[3],
                              long K, const int M[3], const int N[3], int S,
                              R* slots, long P, const long off[3],
-                             hipStream_t s, bool grouped) {
+                             hipStream_t s, bool grouped, bool bf16) {
   if constexpr (std::is_same<R, float>::value) {
     GemmGroup g{};
     bool ok = true;
@@ -2213,7 +2346,7 @@ hipError_t launch_grad_gemm3(const R* const Tin[3], const R* const Tg[3],
   hipError_t e = hipSuccess;
   for (int j = 0; j < 3 && e == hipSuccess; ++j)
     e = launch_grad_gemm<R>(Tin[j], Tg[j], K, M[j], N[j], S, slots, P, off[j],
-                            s);
+                            s, 1, 0, 0, 0, bf16);
   return e;
 }
 
@@ -2466,7 +2599,7 @@ hipError_t backward_t(ModImpl& im, Mod<R>& m, Back<R>& b, const R* g_eval,
         // (the last chunk's products, which nothing runs beside, in one
         // launch; the others one layer at a time, beside the VJPs)
         r = launch_grad_gemm3<R>(ti, tg, Kc, gm, gn, G, b.slots, b.P, go, sg,
-                                 n == 0);
+                                 n == 0, im.mw.packed != nullptr && !im.mw.f32);
       }
       if (r == hipSuccess && ovl) r = hipEventRecord(im.ev[7 + half], s3);
       if (r != hipSuccess) return r;
