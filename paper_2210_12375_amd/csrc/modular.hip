@@ -2250,8 +2250,8 @@ inline GemmPlan plan_grad_gemm(bool f32, long K, int M, int N, int S,
 
 // nb > 1: nb products of the same shape in one launch (grid y), product j
 // reading Tin + j sin and Tg + j sg and adding into its own S slots at
-// slots + j sslot (sslot >= S P).  bf16: BF16 mode, whose large products
-// (the 256 x 256 case) go to the split-BF16 matrix cores.
+// slots + j sslot (sslot >= S P).  bf16: BF16 mode, whose products with
+// at least 256 weight rows and columns go to the split-BF16 matrix cores.
 template <typename R>
 hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
                             int S, R* slots, long P, long off, hipStream_t s,
@@ -2263,7 +2263,7 @@ hipError_t launch_grad_gemm(const R* Tin, const R* Tg, long K, int M, int N,
   const dim3 g(pl.tiles * pl.splits, nb), blk(256);
   const int splits = pl.splits;
   if constexpr (std::is_same<R, float>::value) {
-    if (pl.big && bf16 && nb == 1) {
+    if (bf16 && nb == 1 && M - 1 >= 256 && N >= 256) {
       // 128 x 256 tiles over all M features, about 1024 workgroups
       const int tb = ((M + kBgM - 1) / kBgM) * ((N + kBgN - 1) / kBgN);
       const long by_k = K / 256 > 0 ? K / 256 : 1;
